@@ -1,0 +1,61 @@
+"""Image-quality measures of Appendix B (test infrastructure only).
+
+Correlation coefficient (Appendix B, eq. corrcoeff), Tenenbaum sharpness with
+the Sobel operator normalised by the element count (Appendix B), maximum
+intensity projections, and the relative L2 distance used for parity.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def corrcoef(u1, u2) -> float:
+    """rho = Cov(U1, U2) / sqrt(Var(U1) Var(U2)) over all elements."""
+    a = np.asarray(u1, dtype=np.float64).ravel()
+    b = np.asarray(u2, dtype=np.float64).ravel()
+    a = a - a.mean()
+    b = b - b.mean()
+    return float(np.dot(a, b) / np.sqrt(np.dot(a, a) * np.dot(b, b)))
+
+
+_SOBEL = np.array([[-1.0, 0.0, 1.0], [-2.0, 0.0, 2.0], [-1.0, 0.0, 1.0]])
+
+
+def _conv2_valid(u, k):
+    """2-D correlation of a 2-D array with a 3x3 kernel on interior points."""
+    n0, n1 = u.shape
+    out = np.zeros((n0 - 2, n1 - 2))
+    for a in range(3):
+        for b in range(3):
+            out += k[a, b] * u[a:a + n0 - 2, b:b + n1 - 2]
+    return out
+
+
+def tenenbaum(u) -> float:
+    """Normalised Tenenbaum sharpness: sum of (g*U)^2 + (g^T*U)^2 with the
+    Sobel g, divided by the number of elements of U. For a 3-D volume the
+    2-D operator is applied to every slice along the last axis."""
+    u = np.asarray(u, dtype=np.float64)
+    if u.ndim == 2:
+        slices = [u]
+    else:
+        slices = [u[..., i] for i in range(u.shape[-1])]
+    total = 0.0
+    for s in slices:
+        gx = _conv2_valid(s, _SOBEL)
+        gy = _conv2_valid(s, _SOBEL.T)
+        total += float(np.sum(gx * gx + gy * gy))
+    return total / u.size
+
+
+def mips(u):
+    """Maximum intensity projections along x, y and z."""
+    u = np.asarray(u)
+    return u.max(axis=0), u.max(axis=1), u.max(axis=2)
+
+
+def rel_l2(a, b) -> float:
+    """||a - b||_2 / ||b||_2."""
+    a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
+    b = np.asarray(b, dtype=a.dtype)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))

@@ -1,0 +1,282 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test fixes a part of the oracle with a value the paper or the
+mathematics determines independently of the oracle's own code path:
+brute-force sums on tiny inputs, special cases that reduce to numpy's FFT,
+the paper's index-unit formula (Section 2, eq. equiv_rec), the closed-form
+slab solution of the 1-D wave equation, and exact invariants.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import quality
+from paper_1510_01078_amd import inputs
+
+C = inputs.C_SOUND
+
+
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+# ---------------------------------------------------------------------------
+# whole reconstruction: five-fold sum with no factorisation, tiny sizes
+# ---------------------------------------------------------------------------
+
+def _brute_reconstruct(xy, h, g, dt, c, shape, extent):
+    """f = 1/V sum_K W(K) [sum_m sum_n h dt g e^{-i(Kx x_m + Ky y_m + w t_n)}] e^{iK.r}
+    written as explicit loops over every lattice point (eq. disc_rec then the
+    equispaced inverse), skipping l = 0 and the three Nyquist planes."""
+    nx, ny, nz = shape
+    X, Y, Z = extent
+    m, nt = g.shape
+    t = np.arange(nt) * dt
+    xa = (np.arange(nx) - nx // 2) * X / nx
+    yb = (np.arange(ny) - ny // 2) * Y / ny
+    ze = np.arange(nz) * Z / nz
+    f = np.zeros(shape, dtype=np.complex128)
+    for j in range(-(nx // 2), nx - nx // 2):
+        for k in range(-(ny // 2), ny - ny // 2):
+            for l in range(-(nz // 2), nz - nz // 2):
+                if j == -(nx // 2) or k == -(ny // 2) or l == -(nz // 2) or l == 0:
+                    continue
+                kx, ky, kz = 2 * np.pi * j / X, 2 * np.pi * k / Y, 2 * np.pi * l / Z
+                kabs = np.sqrt(kx * kx + ky * ky + kz * kz)
+                om = c * np.sign(kz) * kabs
+                wgt = 2 * c * abs(kz) / kabs
+                s = 0.0j
+                for mm in range(m):
+                    lat = np.exp(-1j * (kx * xy[mm, 0] + ky * xy[mm, 1]))
+                    s += h[mm] * dt * lat * np.sum(g[mm] * np.exp(-1j * om * t))
+                f += wgt * s * np.exp(1j * (kx * xa[:, None, None] + ky * yb[None, :, None]
+                                            + kz * ze[None, None, :]))
+    return f / (X * Y * Z)
+
+
+def test_bruteforce_tiny_nonsquare():
+    rng = np.random.default_rng(7)
+    shape, extent = (8, 6, 10), (3e-3, 2.5e-3, 4e-3)
+    xy, _ = inputs.random_sensors(16, extent[0], extent[1], rng)
+    h = rng.uniform(0.5, 1.5, 16)
+    h *= extent[0] * extent[1] / h.sum()
+    g = rng.standard_normal((16, 16))
+    dt = 40e-9
+    f_brute = _brute_reconstruct(xy, h, g, dt, C, shape, extent)
+    f, st = oracle.reconstruct(xy, h, g, dt, C, shape, extent, return_stages=True)
+    assert _rel(st["fc"], f_brute) < 1e-12
+    assert _rel(f, f_brute.real) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# stage L: sensors on the output lattice reduce eq. disc_rec to eq. equiv_rec,
+# whose lateral sum is a 2-D DFT (numpy.fft.fft2)
+# ---------------------------------------------------------------------------
+
+def test_stage_lateral_grid_sensors_is_fft2():
+    rng = np.random.default_rng(11)
+    nx, ny, nt = 12, 10, 7
+    X, Y = 5e-3, 4e-3
+    xy, h = inputs.grid_sensors(nx, ny, X, Y)
+    g = rng.standard_normal((nx * ny, nt))
+    dt = 30e-9
+    G = oracle.stage_lateral(xy, h, g, dt, nx, ny, X, Y)
+    F2 = np.fft.fftshift(np.fft.fft2(g.reshape(nx, ny, nt), axes=(0, 1)), axes=(0, 1))
+    j = np.arange(-(nx // 2), nx - nx // 2)
+    k = np.arange(-(ny // 2), ny - ny // 2)
+    sign = ((-1.0) ** j)[:, None, None] * ((-1.0) ** k)[None, :, None]
+    expect = (X / nx) * (Y / ny) * dt * sign * F2
+    assert _rel(G, expect) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# stage T: at lattice points with integer |K| in units of 2*pi/L and
+# dt = L/(c*Nt), omega*t_n = 2*pi*q*n/Nt, so S is a DFT bin (numpy.fft.fft)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("jkl,q", [((0, 3, 4), 5), ((3, 0, -4), 5), ((4, 0, 3), 5), ((0, 0, 5), 5),
+                                   ((2, 3, 6), 7), ((1, 4, -8), 9), ((4, 4, 7), 9), ((-6, 6, 7), 11),
+                                   ((-2, -6, 9), 11), ((0, 0, -3), 3)])
+def test_stage_temporal_pythagorean_bins(jkl, q):
+    rng = np.random.default_rng(3)
+    n, nt, L = 20, 32, 6e-3
+    kx = oracle.lattice(n, L)
+    G = rng.standard_normal((n, n, nt)) + 1j * rng.standard_normal((n, n, nt))
+    dt = L / (C * nt)
+    S = oracle.stage_temporal(G, kx, kx, kx, C, dt)
+    j, k, l = jkl
+    jn, kn, ln = j + n // 2, k + n // 2, l + n // 2
+    expect = np.fft.fft(G[jn, kn])[(int(np.sign(l)) * q) % nt]
+    assert abs(S[jn, kn, ln] - expect) <= 1e-13 * np.abs(G[jn, kn]).sum()
+
+
+# ---------------------------------------------------------------------------
+# inverse: ifftn route vs the explicit triple sum
+# ---------------------------------------------------------------------------
+
+def test_inverse_bruteforce():
+    rng = np.random.default_rng(5)
+    shape, (X, Y, Z) = (8, 6, 10), (2e-3, 3e-3, 5e-3)
+    nx, ny, nz = shape
+    F = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    kx, ky, kz = oracle.lattice(nx, X), oracle.lattice(ny, Y), oracle.lattice(nz, Z)
+    xa = (np.arange(nx) - nx // 2) * X / nx
+    yb = (np.arange(ny) - ny // 2) * Y / ny
+    ze = np.arange(nz) * Z / nz
+    f = np.zeros(shape, dtype=np.complex128)
+    for a in range(nx):
+        for b in range(ny):
+            for e in range(nz):
+                ph = np.exp(1j * (kx[:, None, None] * xa[a] + ky[None, :, None] * yb[b]
+                                  + kz[None, None, :] * ze[e]))
+                f[a, b, e] = np.sum(F * ph) / (X * Y * Z)
+    got = oracle.inverse(F, X, Y, Z, return_complex=True)
+    assert _rel(got, f) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# scale, sign and origin: laterally uniform slab (d'Alembert: g(t) = f(ct)/2)
+# ---------------------------------------------------------------------------
+
+def test_slab_closed_form():
+    n_lat, nz = 8, 64
+    X = 4e-3
+    Z = 6e-3
+    dz = Z / nz
+    dt = dz / C
+    z = np.arange(nz) * dz
+    prof = np.exp(-((z - 0.3 * Z) / (0.05 * Z)) ** 2) + 0.5 * np.exp(-((z - 0.62 * Z) / (0.03 * Z)) ** 2)
+    xy, h = inputs.grid_sensors(n_lat, n_lat, X, X)
+    g = np.tile(0.5 * prof, (n_lat * n_lat, 1))
+    f = oracle.reconstruct(xy, h, g, dt, C, (n_lat, n_lat, nz), (X, X, Z))
+    nyq = np.fft.fft(prof)[nz // 2].real / nz * (-1.0) ** np.arange(nz)
+    expect = prof - prof.mean() - nyq
+    err = np.abs(f - expect[None, None, :]).max() / np.abs(prof).max()
+    assert err < 1e-12
+    # a flipped time sign would reverse depth; the profile is asymmetric
+    assert np.abs(f[0, 0] - (expect[::-1])).max() > 0.1
+
+
+# ---------------------------------------------------------------------------
+# the paper's own index-unit formula (Section 2, eq. equiv_rec): with
+# dx = dy = dz = c*dt and Nx = Ny = Nz = Nt its right side equals F/(dx dy dz)
+# ---------------------------------------------------------------------------
+
+def test_equiv_rec_index_units():
+    rng = np.random.default_rng(17)
+    N = 8
+    dt = 20e-9
+    d = C * dt
+    L = N * d
+    xy, h = inputs.grid_sensors(N, N, L, L)
+    g = rng.standard_normal((N * N, N))
+    _, st = oracle.reconstruct(xy, h, g, dt, C, (N, N, N), (L, L, L), return_stages=True)
+    Fnat = st["F"]
+    idx = np.arange(-N // 2, N // 2)
+    gm = g.reshape(N, N, N)      # [mx + N/2, my + N/2, n]
+    n = np.arange(N)
+    for jx in idx:
+        for jy in idx:
+            for l in idx:
+                if l == 0 or jx == -N // 2 or jy == -N // 2 or l == -N // 2:
+                    continue
+                kappa = np.sign(l) * np.sqrt(jx * jx + jy * jy + l * l)
+                inner = np.zeros(N, dtype=np.complex128)
+                for mx in idx:
+                    for my in idx:
+                        inner += np.exp(-2j * np.pi * (jx * mx + jy * my) / N) * gm[mx + N // 2, my + N // 2]
+                paper = (2 * l / kappa) * np.sum(np.exp(-2j * np.pi * kappa * n / N) * inner)
+                ours = Fnat[jx + N // 2, jy + N // 2, l + N // 2] / d ** 3
+                assert abs(ours - paper) <= 1e-12 * (1 + abs(paper))
+
+
+# ---------------------------------------------------------------------------
+# invariants
+# ---------------------------------------------------------------------------
+
+def _small_random_problem(seed=21, m=24, nt=20, shape=(8, 8, 12), extent=(3e-3, 3e-3, 4e-3)):
+    rng = np.random.default_rng(seed)
+    p = inputs.random_problem(rng, m, nt, shape, extent, dt=25e-9)
+    return p, rng
+
+
+def test_translation_by_one_voxel():
+    p, _ = _small_random_problem()
+    X = p.extent[0]
+    dx = X / p.shape[0]
+    xs = p.xy.copy()
+    xs[:, 0] += dx
+    xs[:, 0] = np.where(xs[:, 0] >= X / 2, xs[:, 0] - X, xs[:, 0])
+    f0 = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    f1 = oracle.reconstruct(xs, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    assert np.abs(f1 - np.roll(f0, 1, axis=0)).max() <= 1e-12 * np.abs(f0).max()
+
+
+def test_real_image_and_hermitian_spectrum():
+    p, _ = _small_random_problem(seed=22)
+    _, st = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent, return_stages=True)
+    fc = st["fc"]
+    assert np.abs(fc.imag).max() <= 1e-13 * np.abs(fc.real).max()
+    F = st["F"]
+    # F(-K) = conj F(K) on the non-Nyquist part (natural order index i -> N - i)
+    Fi = F[1:, 1:, 1:]
+    assert np.abs(Fi - np.conj(Fi[::-1, ::-1, ::-1])).max() <= 1e-12 * np.abs(F).max()
+
+
+def test_linearity():
+    p, rng = _small_random_problem(seed=23)
+    g2 = rng.standard_normal(p.g.shape)
+    a, b = 0.7, -1.9
+    f1 = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    f2 = oracle.reconstruct(p.xy, p.h, g2, p.dt, p.c, p.shape, p.extent)
+    f3 = oracle.reconstruct(p.xy, p.h, a * p.g + b * g2, p.dt, p.c, p.shape, p.extent)
+    assert np.abs(f3 - (a * f1 + b * f2)).max() <= 1e-12 * np.abs(f3).max()
+
+
+def test_spectrum_at_matches_full():
+    p, rng = _small_random_problem(seed=24)
+    _, st = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent, return_stages=True)
+    nx, ny, nz = p.shape
+    jkl = np.stack([rng.integers(-(nx // 2), nx - nx // 2, 40), rng.integers(-(ny // 2), ny - ny // 2, 40),
+                    rng.integers(-(nz // 2), nz - nz // 2, 40)], 1)
+    got = oracle.spectrum_at(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent, jkl)
+    ref = st["F"][jkl[:, 0] + nx // 2, jkl[:, 1] + ny // 2, jkl[:, 2] + nz // 2]
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(st["F"]).max()
+
+
+def test_half_spectrum_layout():
+    rng = np.random.default_rng(2)
+    F = rng.standard_normal((6, 4, 8))
+    H = oracle.half_spectrum(F)
+    assert H.shape == (6, 4, 5)
+    # [j mod Nx, k mod Ny, l] with natural index j + Nx/2
+    for j in (-3, -1, 0, 2):
+        for k in (-2, 0, 1):
+            for l in range(0, 4):
+                assert H[j % 6, k % 4, l] == F[j + 3, k + 2, l + 4]
+            assert H[j % 6, k % 4, 4] == F[j + 3, k + 2, 0]
+
+
+# ---------------------------------------------------------------------------
+# physics, approximate: one ball (tiny workload geometry)
+# ---------------------------------------------------------------------------
+
+def test_ball_physics_tiny_workload():
+    p = inputs.config_problem(0)
+    f = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    nx, ny, nz = p.shape
+    X, Y, Z = p.extent
+    cx, cy, cz = p.balls.centres[0]
+    R = p.balls.radii[0]
+    a, b, e = np.unravel_index(np.argmax(f), f.shape)
+    pos = np.array([(a - nx // 2) * X / nx, (b - ny // 2) * Y / ny, e * Z / nz])
+    assert np.linalg.norm(pos - [cx, cy, cz]) < R
+    # no ghost at the mirror depth Z - cz (a flipped time sign would put it there)
+    em = int(round((Z - cz) / (Z / nz))) % nz
+    ec = int(round(cz / (Z / nz)))
+    assert np.abs(f[:, :, em]).max() < 0.2 * np.abs(f[:, :, ec]).max()
+    truth = inputs.voxelise_balls(p.balls, nx, ny, nz, X, Y, Z)
+    rho = quality.corrcoef(f, truth)
+    # threshold frozen from the oracle's own value at the time of writing (0.6 ...),
+    # with margin; limited view keeps it well below 1
+    assert rho > 0.5
