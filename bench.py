@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Throughput of NEDNER-NUFFT photoacoustic reconstruction on one MI355X.
+
+One step = one pat_reconstruct call (all stages: temporal FFT, lateral
+spread, lateral FFTs with deconvolution, temporal interpolation and weight,
+inverse 3-D FFT) over the resident traces of one synthetic problem. The
+default workload is 128x128 warped and jittered sensors on a 25 mm plane,
+2048 samples at 60 MHz, a 40-tube vessel phantom, reconstructed to 256^3 in
+FP32. Prints one JSON line on stdout; progress goes to stderr.
+
+The CPU-baseline leg times the FP64 oracle on a bounded sample of the same
+workload (a few lateral x-modes, all y-modes and depths), extrapolates to the
+full grid, and compares the GPU spectrum with the oracle on that sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "recon voxels/s at 128² sensors×2048 t→256³; spread GB/s vs HBM peak"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    0: "16x16 warped sensors, 128 samples at 20 MHz, one ball -> 32^3",
+    1: "64x64 warped sensors, 1024 samples at 40 MHz, 8 balls + 1% noise -> 128^3",
+    2: "128x128 warped sensors (+-5% jitter) on 25 mm, 2048 samples at 60 MHz, 40-tube vessel phantom -> 256^3",
+    4: "96x96 warped sensors on 20 mm, 1536 samples at 40 MHz, 8 balls -> 192^3",
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def spread_bytes(plan, p, eb):
+    """Algorithmic bytes of one spread launch: read the per-sensor band values,
+    write the oversampled grid once, read the sensor tables and tile lists."""
+    info = plan.info
+    nb, nxo, nyo = info["band_bins"], info["nx_over"], info["ny_over"]
+    w = plan._desc.width_xy
+    m = p.m
+    read_bins = m * nb * 2 * eb
+    write_grid = nb * nxo * nyo * 2 * eb
+    tables = m * (2 * w * eb + 2 * 4) + 4 * (info["spread_tiles"] + 1) + 4 * info["spread_pairs"]
+    return read_bins + write_grid + tables
+
+
+def stage_bytes(plan, p, eb):
+    """Algorithmic bytes per launch of every stage (one pass over each array)."""
+    info = plan.info
+    nb, nxo, nyo, nto = info["band_bins"], info["nx_over"], info["ny_over"], info["nt_over"]
+    Nx, Ny, Nz = p.shape
+    c = 2 * eb
+    lh = Nz // 2 + 1
+    return [
+        p.m * p.nt * eb + p.m * nb * c,                       # temporal: traces in, band out
+        spread_bytes(plan, p, eb),                            # spread
+        nb * nyo * nxo * c + nb * Nx * nyo * c,               # FFT along x with crop
+        nb * Nx * nyo * c + Nx * Ny * nb * c,                 # FFT along y, crop, deconvolve
+        Nx * Ny * nb * c + Nx * Ny * lh * c,                  # gather + weight
+        3 * 2 * Nx * Ny * lh * c // 2 + Nx * Ny * lh * c + Nx * Ny * Nz * eb,  # inverse passes
+    ]
+
+
+def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
+    """Time the FP64 oracle on `nsample` lateral x-modes (all y-modes, all
+    depths), extrapolate to the full grid (plus the full inverse transform),
+    and compare the GPU half spectrum with the oracle on the sample."""
+    import oracle
+    from threadpoolctl import threadpool_info
+
+    Nx, Ny, Nz = p.shape
+    X, Y, Z = p.extent
+    rng = np.random.default_rng(seed)
+    rows = np.sort(rng.choice(np.arange(1, Nx), size=nsample, replace=False))  # natural-order x positions
+    kx, ky, kz = oracle.lattice(Nx, X), oracle.lattice(Ny, Y), oracle.lattice(Nz, Z)
+    t0 = time.perf_counter()
+    G = oracle.stage_lateral(p.xy, p.h, p.g, p.dt, Nx, Ny, X, Y, j_index=rows)
+    S = oracle.stage_temporal(G, kx[rows], ky, kz, p.c, p.dt)
+    F = oracle.apply_weight(S, kx, ky, kz, p.c, j_index=rows)
+    t_sample = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    oracle.inverse(np.ones(p.shape, dtype=np.complex128), X, Y, Z)
+    t_inv = time.perf_counter() - t1
+    t_full = t_sample * Nx / nsample + t_inv
+    # parity on the sample: GPU layout [j mod Nx][k mod Ny][l], l = 0..Nz/2
+    jj = (rows - Nx // 2) % Nx
+    lz = np.arange(Nz // 2 + 1)
+    ref = np.fft.ifftshift(F, axes=1)[:, :, (lz + Nz // 2) % Nz]
+    got = gpu_spectrum[jj]
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    blas = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+    cores = max([os.cpu_count() or 1] + [b or 1 for b in blas]) if blas else (os.cpu_count() or 1)
+    try:
+        cores = min(cores, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        pass
+    return {
+        "value": float(np.prod(p.shape) / t_full),
+        "unit": "voxels/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": f"FP64 direct-sum oracle on {nsample} of {Nx} lateral x-modes (all {Ny} y-modes, all {Nz} "
+                  f"depths) in {t_sample:.1f} s, extrapolated linearly in x-modes plus the full inverse "
+                  f"transform ({t_inv:.1f} s)",
+        "seconds_sample": round(t_sample, 3),
+        "seconds_extrapolated": round(t_full, 1),
+        "gpu_vs_oracle_rel_l2_on_sample": rel,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_kahan", "fp64"])
+    ap.add_argument("--kernel", default="kaiser_bessel", choices=["kaiser_bessel", "gaussian"])
+    ap.add_argument("--sigma-xy", type=float, default=2.0)
+    ap.add_argument("--width-xy", type=int, default=8)
+    ap.add_argument("--sigma-t", type=float, default=2.0)
+    ap.add_argument("--width-t", type=int, default=8)
+    ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--cpu-sample", type=int, default=8, help="lateral x-modes in the oracle sample")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1510_01078_amd import Plan, inputs
+
+    dev = torch.device("cuda", 0)
+    log(f"generating workload {args.config}: {WORKLOADS[args.config]}")
+    p = inputs.config_problem(args.config)
+    log(f"M={p.m} Nt={p.nt} grid={p.shape}; building plan ({args.precision}, {args.kernel}, "
+        f"sigma {args.sigma_xy}/{args.sigma_t}, w {args.width_xy}/{args.width_t})")
+    plan = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, sigma_xy=args.sigma_xy,
+                width_xy=args.width_xy, sigma_t=args.sigma_t, width_t=args.width_t, kernel=args.kernel,
+                precision=args.precision, device=dev)
+    eb = 8 if args.precision == "fp64" else 4
+    g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, plan.dtype)
+    out = torch.empty(p.shape, dtype=plan.dtype, device=dev)
+    log(f"plan info {plan.info}")
+
+    for _ in range(args.warmup):
+        plan.reconstruct(g, out=out)
+    torch.cuda.synchronize(dev)
+    log("warmup done")
+
+    plan.timing_begin(args.steps)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.reconstruct(g, out=out)
+    torch.cuda.synchronize(dev)
+    elapsed = time.perf_counter() - t0
+    stage_ms, calls = plan.timing_end()
+    log(f"timed {args.steps} steps in {elapsed:.4f} s")
+    ms_step = 1000.0 * elapsed / args.steps
+    voxels = float(np.prod(p.shape))
+    value = voxels / (elapsed / args.steps)
+
+    sb = stage_bytes(plan, p, eb)
+    avg_ms = [s / max(1, calls) for s in stage_ms]
+    names = ["temporal_fft", "spread", "lateral_fft_x", "lateral_fft_y_deconv", "gather_weight", "inverse_fft"]
+    stages = {n: {"ms": round(a, 5), "bytes": int(b), "GB_s": round(b / (a * 1e-3) / 1e9, 1) if a > 0 else None}
+              for n, a, b in zip(names, avg_ms, sb)}
+    spread_ms = avg_ms[1]
+    achieved = sb[1] / (spread_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spread",
+                "bytes_per_launch": int(sb[1]), "ms_per_launch": round(spread_ms, 5)}
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "sensors": p.m, "samples": p.nt,
+                   "grid": list(p.shape), "precision": args.precision, "kernel": args.kernel,
+                   "sigma_xy": args.sigma_xy, "width_xy": args.width_xy, "sigma_t": args.sigma_t,
+                   "width_t": args.width_t, "band_bins": plan.info["band_bins"],
+                   "oversampled_grid": [plan.info["nx_over"], plan.info["ny_over"], plan.info["nt_over"]]},
+        "roofline": roofline,
+        "stages": stages,
+        "cpu_baseline": None,
+    }
+    if args.cpu_baseline == "on":
+        log("gpu spectrum for the sample check")
+        spec = plan.spectrum(g)
+        torch.cuda.synchronize(dev)
+        spec_np = spec.cpu().numpy().astype(np.complex128)
+        log("cpu baseline (oracle on a sample) ...")
+        result["cpu_baseline"] = cpu_baseline(p, spec_np, args.cpu_sample)
+        log(f"cpu baseline done: {result['cpu_baseline']['seconds_sample']} s sample")
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * pat_nufft.h -- C ABI of the MI355X (gfx950) NEDNER-NUFFT library for planar
+ * photoacoustic reconstruction.
+ *
+ * Problem (Schmid, Glatz, Zabihian, Liu, Drexler, Scherzer, "Non-Equispaced
+ * Grid Sampling in Photoacoustics with a Non-Uniform FFT", Section 2):
+ * pressure traces g[m][n] are recorded at M sensors x_m = (x_m, y_m) on the
+ * plane z = 0 (not necessarily equispaced, each with detector area h_m,
+ * sum h_m = X*Y) at times t_n = n*dt. The initial pressure f on the cube
+ * [-X/2,X/2) x [-Y/2,Y/2) x [0,Z) follows from the exact Fourier inversion
+ * (Section 2, eq. exact), discretised over non-equispaced sensors
+ * (Section 2, eq. disc_rec):
+ *
+ *   F(K) = W(K) * sum_n e^{-i omega(K) t_n} sum_m h_m dt g[m][n] e^{-i(Kx x_m + Ky y_m)}
+ *   omega(K) = c sign(Kz) |K|,  W(K) = 2 c |Kz| / |K|   (W = 0 on Kz = 0)
+ *   f(x_a, y_b, z_e) = 1/(XYZ) sum_K F(K) e^{i(Kx x_a + Ky y_b + Kz z_e)}
+ *
+ * on the lattice Kx = 2 pi j/X, Ky = 2 pi k/Y, Kz = 2 pi l/Z with
+ * j in [-Nx/2, Nx/2), k in [-Ny/2, Ny/2), l in [-Nz/2, Nz/2); the planes
+ * j = -Nx/2, k = -Ny/2, l = -Nz/2 are set to zero. The output voxels are
+ * x_a = (a - Nx/2) X/Nx, y_b = (b - Ny/2) Y/Ny, z_e = e Z/Nz.
+ *
+ * The library evaluates this with the NEDNER-NUFFT of Section 3: a
+ * non-equispaced-range NUFFT in time (eqs. NUDFT1, NER_NUFFT, PSI), a
+ * non-equispaced-data NUFFT over the sensor plane (eqs. NUDFT2, NED_NUFFT)
+ * and an equispaced inverse FFT, with precomputed window tables
+ * (Section 5.2: precomputing the window values for a fixed discretisation).
+ * The result approximates the sum above within the window error for the
+ * chosen oversampling and width.
+ *
+ * Memory and execution model
+ *  - All data pointers passed to pat_reconstruct / pat_spectrum /
+ *    pat_forward / pat_adjoint are DEVICE pointers on the device that was
+ *    current when the plan was created. The plan descriptor's sensor arrays
+ *    are HOST pointers; the plan copies them.
+ *  - Element type: float for PAT_FP32 and PAT_FP32_KAHAN, double for PAT_FP64.
+ *    Complex values are (re, im) pairs of that type.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream). Every
+ *    compute call only enqueues work on it: no host synchronisation and no
+ *    device allocation, so calls can be captured into a HIP graph.
+ *  - The caller owns g, f, fhat, the workspace and the stream. The plan owns
+ *    its device tables (allocated through the descriptor's callbacks, or
+ *    hipMalloc when they are NULL) and frees them in nufft_plan_destroy.
+ *  - A plan is immutable after creation; concurrent calls on one plan are
+ *    allowed when each uses its own workspace (timing, when enabled, is not
+ *    thread-safe).
+ *  - Errors are returned as status codes; nothing throws across the ABI.
+ *    Argument validation happens before anything is enqueued, so a call that
+ *    fails validation leaves its outputs untouched. NaN inputs propagate.
+ */
+#ifndef PAT_NUFFT_H
+#define PAT_NUFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PAT_OK = 0,
+  PAT_ERR_INVALID_ARGUMENT = 1, /* NULL pointer, bad size, sensor outside the plane, ... */
+  PAT_ERR_UNSUPPORTED = 2,      /* size the FFTs or kernels cannot represent */
+  PAT_ERR_ALLOC = 3,            /* device allocation (or the alloc callback) failed */
+  PAT_ERR_HIP = 4,              /* a HIP runtime call or kernel launch failed */
+  PAT_ERR_NOT_IMPLEMENTED = 5
+} pat_status;
+
+typedef enum {
+  PAT_FP64 = 0,       /* double data, double tables: the plain comparison form */
+  PAT_FP32 = 1,       /* float data and arithmetic; tables and omega(K) map computed in double */
+  PAT_FP32_KAHAN = 2  /* as PAT_FP32 with compensated (Kahan) summation in the spread */
+} pat_precision;
+
+/* Window Psi of Section 3.1 (eq. NUFFT1): compactly supported, positive on
+ * the band, with an analytic or quadrature Fourier transform. */
+typedef enum {
+  PAT_KERNEL_GAUSSIAN = 0,       /* truncated Gaussian (Greengard-Lee width rule) */
+  PAT_KERNEL_KAISER_BESSEL = 1   /* Kaiser-Bessel, the window named in Section 3.1 */
+} pat_kernel;
+
+typedef struct pat_plan_desc {
+  int32_t n_sensors;         /* M >= 1 */
+  int32_t n_t;               /* Nt >= 2, samples per trace */
+  double dt;                 /* sampling step in s, > 0 */
+  double c;                  /* speed of sound in m/s, > 0 */
+  const double* sensor_xy;   /* HOST [M][2] sensor positions in metres, plane-centred;
+                                each must satisfy -X/2 <= x < X/2 and -Y/2 <= y < Y/2 */
+  const double* sensor_h;    /* HOST [M] detector areas in m^2 (sum = X*Y), or NULL for X*Y/M */
+  int32_t nx, ny, nz;        /* output grid, each even and >= 4 */
+  double lx, ly, lz;         /* extents X, Y, Z in metres, > 0 */
+  double sigma_xy;           /* lateral oversampling factor, >= 1.1 (grid = smooth(sigma*N)) */
+  int32_t width_xy;          /* lateral window footprint w in grid points, even, 2..16 */
+  double sigma_t;            /* temporal oversampling factor, >= 1.1 */
+  int32_t width_t;           /* temporal window footprint, even, 2..16 */
+  pat_kernel kernel;
+  pat_precision precision;
+  /* Optional device allocator (e.g. a framework's caching allocator). Both
+   * NULL: the library uses hipMalloc/hipFree. alloc must return memory on the
+   * current device aligned to at least 256 bytes, or NULL on failure. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* alloc_ctx;
+} pat_plan_desc;
+
+typedef struct pat_plan pat_plan;
+
+/* Sizes the plan derived; filled by pat_plan_get_info. */
+typedef struct pat_plan_info {
+  int32_t nx_over, ny_over;  /* oversampled lateral grid */
+  int32_t nt_over;           /* oversampled temporal FFT length */
+  int32_t band_lo;           /* first oversampled temporal bin kept (may be < 0) */
+  int32_t band_bins;         /* number of temporal bins kept */
+  int32_t time_origin;       /* centring offset n0 = Nt/2 of the temporal window */
+  int32_t element_bytes;     /* 4 or 8 */
+  int32_t spread_tiles;      /* lateral spread tiles */
+  int64_t spread_pairs;      /* (sensor, tile) incidences in the spread lists */
+  size_t workspace_bytes;
+  size_t table_bytes;        /* device bytes owned by the plan */
+} pat_plan_info;
+
+/* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, NULL
+ * pointers, zero sizes. Returns PAT_ERR_INVALID_ARGUMENT if desc is NULL. */
+pat_status pat_plan_desc_init(pat_plan_desc* desc);
+
+/* Build a plan for one sensor geometry and output grid (the precomputation
+ * of window tables of Section 5.2). Validates the descriptor, computes in
+ * double precision on the host each sensor's oversampled-grid coordinates
+ * and window weights, the spread tile lists, the deconvolution and
+ * deapodisation vectors and the FFT twiddles, and copies them to the device
+ * with hipMemcpyAsync on `stream` (hipStream_t) followed by a stream
+ * synchronisation. On success *out owns the plan; on failure *out is NULL. */
+pat_status nufft_plan(const pat_plan_desc* desc, void* stream, pat_plan** out);
+
+/* Workspace bytes every compute call on this plan needs (>= 256-byte aligned). */
+pat_status nufft_plan_workspace_size(const pat_plan* plan, size_t* bytes);
+
+pat_status pat_plan_get_info(const pat_plan* plan, pat_plan_info* info);
+
+/* Release the plan and its device tables. NULL is accepted and ignored.
+ * Synchronises the device before freeing. */
+pat_status nufft_plan_destroy(pat_plan* plan);
+
+/* f = R g: reconstruction (Section 2, eq. disc_rec; Section 3, NEDNER steps).
+ * g: DEVICE [M][Nt] real, one trace per sensor in descriptor order.
+ * f: DEVICE [Nx][Ny][Nz] real, depth-contiguous; overwritten.
+ * workspace: DEVICE, nufft_plan_workspace_size bytes, 256-byte aligned.
+ * g, f and workspace must not overlap. */
+pat_status pat_reconstruct(pat_plan* plan, const void* g, void* f, void* workspace, void* stream);
+
+/* fhat = F: the weighted spectrum before the inverse transform (the Fourier
+ * coefficients of f that eq. disc_rec approximates), as the non-negative
+ * half along z: DEVICE complex [Nx][Ny][Nz/2+1] indexed [j mod Nx][k mod Ny][l],
+ * l = 0..Nz/2; the l = 0, l = Nz/2, j = -Nx/2 and k = -Ny/2 entries are 0.
+ * F(-K) = conj F(K) gives the rest. */
+pat_status pat_spectrum(pat_plan* plan, const void* g, void* fhat, void* workspace, void* stream);
+
+/* g = A f: the forward model on the Fourier lattice (not yet implemented;
+ * returns PAT_ERR_NOT_IMPLEMENTED). */
+pat_status pat_forward(pat_plan* plan, const void* f, void* g, void* workspace, void* stream);
+
+/* f = A* g: the adjoint of pat_forward (not yet implemented). */
+pat_status pat_adjoint(pat_plan* plan, const void* g, void* f, void* workspace, void* stream);
+
+/* Per-stage device timing with HIP events recorded on the call's stream.
+ * pat_timing_begin(plan, n) creates events for up to n subsequent compute
+ * calls (allocation happens here, not in the compute calls). pat_timing_end
+ * synchronises on the last event, writes the summed milliseconds of each
+ * stage to ms[0..nstage-1] (nstage <= PAT_TIMING_STAGES), the number of
+ * recorded calls to *calls, and destroys the events. Stages:
+ * 0 temporal FFT, 1 lateral spread, 2 lateral FFT along x, 3 lateral FFT
+ * along y with deconvolution, 4 temporal gather and weight, 5 inverse FFT. */
+#define PAT_TIMING_STAGES 6
+pat_status pat_timing_begin(pat_plan* plan, int32_t max_calls);
+pat_status pat_timing_end(pat_plan* plan, double* ms, int32_t nstage, int32_t* calls);
+
+const char* pat_status_str(pat_status status);
+
+/* Library version string. */
+const char* pat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAT_NUFFT_H */

@@ -67,11 +67,12 @@ def omega_and_weight(kx, ky, kz, c):
     return omega, w
 
 
-def stage_lateral(xy, h, g, dt, nx, ny, X, Y) -> np.ndarray:
+def stage_lateral(xy, h, g, dt, nx, ny, X, Y, j_index=None) -> np.ndarray:
     """Stage L: G[j,k,n] = sum_m h_m dt g[m,n] exp(-i(Kx_j x_m + Ky_k y_m)).
 
     The sum over m is a complex matrix product per j (a library GEMM).
-    Returns complex128 [nx, ny, Nt] in natural index order (j = -nx/2 first).
+    Returns complex128 [nx, ny, Nt] in natural index order (j = -nx/2 first);
+    with `j_index` (natural-order positions) only those rows, in that order.
     """
     xy = np.asarray(xy, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)
@@ -80,15 +81,13 @@ def stage_lateral(xy, h, g, dt, nx, ny, X, Y) -> np.ndarray:
     ky = lattice(ny, Y)
     c_in = hw[:, None] * g                                   # [M, Nt]
     ey = np.exp(-1j * np.outer(ky, xy[:, 1]))                # [ny, M]
-    out = np.empty((nx, ny, g.shape[1]), dtype=np.complex128)
+    rows = np.arange(nx) if j_index is None else np.asarray(j_index)
+    out = np.empty((len(rows), ny, g.shape[1]), dtype=np.complex128)
 
-    def one(j):
+    for i, j in enumerate(rows):
         ex = np.exp(-1j * kx[j] * xy[:, 0])                  # [M]
         a = ey * ex[None, :]                                 # [ny, M]
-        out[j] = (a.real @ c_in) + 1j * (a.imag @ c_in)
-
-    for j in range(nx):
-        one(j)
+        out[i] = (np.ascontiguousarray(a.real) @ c_in) + 1j * (np.ascontiguousarray(a.imag) @ c_in)
     return out
 
 
@@ -119,12 +118,14 @@ def stage_temporal(G, kx, ky, kz, c, dt, l_index=None) -> np.ndarray:
     return S
 
 
-def apply_weight(S, kx, ky, kz, c) -> np.ndarray:
+def apply_weight(S, kx, ky, kz, c, j_index=None) -> np.ndarray:
     """F = W*S with W = 2c|Kz|/|K| (0 on Kz = 0), then zero the Nyquist planes
-    j = -nx/2, k = -ny/2, l = -nz/2 (index 0 of each natural-order axis)."""
-    _, w = omega_and_weight(kx[:, None, None], ky[None, :, None], kz[None, None, :], c)
+    j = -nx/2, k = -ny/2, l = -nz/2 (index 0 of each natural-order axis).
+    With `j_index`, S holds only those natural-order x rows of the lattice."""
+    rows = np.arange(len(kx)) if j_index is None else np.asarray(j_index)
+    _, w = omega_and_weight(kx[rows][:, None, None], ky[None, :, None], kz[None, None, :], c)
     F = w * S
-    F[0, :, :] = 0.0
+    F[rows == 0, :, :] = 0.0
     F[:, 0, :] = 0.0
     F[:, :, 0] = 0.0
     return F
@@ -195,7 +196,7 @@ def spectrum_at(xy, h, g, dt, c, shape, extent, jkl) -> np.ndarray:
     for s in range(0, len(jkl), step):
         sl = slice(s, s + step)
         lat = np.exp(-1j * (np.outer(kx[sl], xy[:, 0]) + np.outer(ky[sl], xy[:, 1])))  # [p, M]
-        Gs = (lat.real @ c_in) + 1j * (lat.imag @ c_in)                               # [p, Nt]
+        Gs = (np.ascontiguousarray(lat.real) @ c_in) + 1j * (np.ascontiguousarray(lat.imag) @ c_in)  # [p, Nt]
         et = np.exp(-1j * np.outer(om[sl], t))                                          # [p, Nt]
         out[sl] = w[sl] * np.sum(Gs * et, axis=1)
     nyq = (jkl[:, 0] == -(nx // 2)) | (jkl[:, 1] == -(ny // 2)) | (jkl[:, 2] == -(nz // 2))

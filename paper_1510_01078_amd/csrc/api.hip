@@ -1,0 +1,568 @@
+// Host side of the C ABI: descriptor validation, the plan's precomputed
+// tables (Section 5.2: window values precomputed for a fixed discretisation),
+// workspace layout and the enqueueing of the stage kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pat_nufft.h"
+#include "window.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+inline bool smooth235(long n) {
+  if (n < 1) return false;
+  for (int p : {2, 3, 5})
+    while (n % p == 0) n /= p;
+  return n == 1;
+}
+
+// smallest even 2,3,5-smooth integer >= n
+inline int next_smooth_even(double v) {
+  long n = (long)std::ceil(v - 1e-9);
+  if (n < 2) n = 2;
+  while (!(smooth235(n) && n % 2 == 0)) ++n;
+  return (int)n;
+}
+
+bool radix_plan(int n, patk::FftRaw& f) {
+  f.n = n;
+  f.npass = 0;
+  int r = n;
+  auto push = [&](int R) {
+    if (f.npass >= 16) return false;
+    f.radix[f.npass++] = R;
+    r /= R;
+    return true;
+  };
+  while (r % 8 == 0)
+    if (!push(8)) return false;
+  while (r % 4 == 0)
+    if (!push(4)) return false;
+  while (r % 2 == 0)
+    if (!push(2)) return false;
+  while (r % 5 == 0)
+    if (!push(5)) return false;
+  while (r % 3 == 0)
+    if (!push(3)) return false;
+  return r == 1;
+}
+
+struct HostBlob {
+  std::vector<unsigned char> bytes;
+  size_t add(const void* src, size_t n) {
+    size_t off = align_up(bytes.size());
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+template <typename T>
+size_t add_real(HostBlob& b, const std::vector<double>& v) {
+  std::vector<T> t(v.begin(), v.end());
+  return b.add(t.data(), t.size() * sizeof(T));
+}
+
+template <typename T>
+size_t add_twiddles(HostBlob& b, int n) {
+  std::vector<T> t(2 * size_t(n));
+  for (int i = 0; i < n; ++i) {
+    const double a = -2.0 * M_PI * double(i) / double(n);
+    t[2 * i] = T(std::cos(a));
+    t[2 * i + 1] = T(std::sin(a));
+  }
+  return b.add(t.data(), t.size() * sizeof(T));
+}
+
+}  // namespace
+
+struct pat_plan {
+  pat_plan_desc d;
+  int device = 0;
+  bool fp64 = false;
+  patk::DevPlan dp;
+  void* dev = nullptr;
+  size_t dev_bytes = 0;
+  size_t off_B = 0;     // workspace: region A at 0 (grid / lateral spectra), region B at off_B
+  size_t ws_bytes = 0;
+  int64_t spread_pairs = 0;
+  std::vector<hipEvent_t> ev;  // PAT_TIMING_STAGES+1 per recorded call
+  int ev_max = 0;
+  int ev_used = 0;
+};
+
+namespace {
+
+pat_status validate(const pat_plan_desc* d) {
+  if (!d) return PAT_ERR_INVALID_ARGUMENT;
+  if (d->n_sensors < 1 || d->n_t < 2) return PAT_ERR_INVALID_ARGUMENT;
+  if (!(d->dt > 0.0) || !std::isfinite(d->dt) || !(d->c > 0.0) || !std::isfinite(d->c)) return PAT_ERR_INVALID_ARGUMENT;
+  if (!d->sensor_xy) return PAT_ERR_INVALID_ARGUMENT;
+  for (int32_t n : {d->nx, d->ny, d->nz})
+    if (n < 4 || (n % 2) != 0) return PAT_ERR_INVALID_ARGUMENT;
+  for (double L : {d->lx, d->ly, d->lz})
+    if (!(L > 0.0) || !std::isfinite(L)) return PAT_ERR_INVALID_ARGUMENT;
+  if (!(d->sigma_xy >= 1.1 && d->sigma_xy <= 4.0) || !(d->sigma_t >= 1.1 && d->sigma_t <= 4.0))
+    return PAT_ERR_INVALID_ARGUMENT;
+  if (d->width_xy < 2 || d->width_xy > 16 || (d->width_xy % 2) || d->width_t < 2 || d->width_t > 16 ||
+      (d->width_t % 2))
+    return d->width_xy > 16 || d->width_t > 16 ? PAT_ERR_UNSUPPORTED : PAT_ERR_INVALID_ARGUMENT;
+  if (d->kernel != PAT_KERNEL_GAUSSIAN && d->kernel != PAT_KERNEL_KAISER_BESSEL) return PAT_ERR_INVALID_ARGUMENT;
+  if (d->precision != PAT_FP64 && d->precision != PAT_FP32 && d->precision != PAT_FP32_KAHAN)
+    return PAT_ERR_INVALID_ARGUMENT;
+  if ((d->alloc == nullptr) != (d->free == nullptr)) return PAT_ERR_INVALID_ARGUMENT;
+  const double hx = 0.5 * d->lx, hy = 0.5 * d->ly;
+  for (int32_t m = 0; m < d->n_sensors; ++m) {
+    const double x = d->sensor_xy[2 * m], y = d->sensor_xy[2 * m + 1];
+    if (!(x >= -hx && x < hx && y >= -hy && y < hy)) return PAT_ERR_INVALID_ARGUMENT;
+    if (d->sensor_h && !(d->sensor_h[m] > 0.0 && std::isfinite(d->sensor_h[m]))) return PAT_ERR_INVALID_ARGUMENT;
+  }
+  return PAT_OK;
+}
+
+void* dev_alloc(const pat_plan_desc& d, size_t bytes) {
+  if (d.alloc) return d.alloc(bytes, d.alloc_ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(const pat_plan_desc& d, void* p) {
+  if (!p) return;
+  if (d.free)
+    d.free(p, d.alloc_ctx);
+  else
+    (void)hipFree(p);
+}
+
+template <typename T>
+pat_status build_tables(pat_plan* P, hipStream_t stream) {
+  const pat_plan_desc& d = P->d;
+  patk::DevPlan& dp = P->dp;
+  const int M = d.n_sensors, Nt = d.n_t;
+  dp.M = M;
+  dp.Nt = Nt;
+  dp.Nx = d.nx;
+  dp.Ny = d.ny;
+  dp.Nz = d.nz;
+  dp.n_x = next_smooth_even(d.sigma_xy * d.nx);
+  dp.n_y = next_smooth_even(d.sigma_xy * d.ny);
+  dp.n_t = next_smooth_even(d.sigma_t * Nt);
+  dp.n0 = Nt / 2;
+  dp.w_xy = d.width_xy;
+  dp.w_t = d.width_t;
+  dp.kahan = d.precision == PAT_FP32_KAHAN;
+  const size_t cxb = 2 * sizeof(T);
+  // FFT lengths the LDS kernels handle (one transform of n complex per work-group within 64 KiB)
+  if ((size_t)dp.n_t * cxb > 65536 || (size_t)(dp.n_x + 1) * cxb > 65536 || (size_t)(dp.n_y + 1) * cxb > 65536 ||
+      (size_t)(d.nx + 1) * cxb > 65536 || (size_t)(d.ny + 1) * cxb > 65536 || (size_t)(d.nz + 1) * cxb > 65536)
+    return PAT_ERR_UNSUPPORTED;
+  if (dp.n_x > 4096 || dp.n_y > 4096 || d.nx > 2048 || d.ny > 2048 || d.nz > 2048) return PAT_ERR_UNSUPPORTED;
+  if (!radix_plan(dp.n_t, dp.f_nt) || !radix_plan(dp.n_x, dp.f_nx) || !radix_plan(dp.n_y, dp.f_ny) ||
+      !radix_plan(d.nx, dp.f_Nx) || !radix_plan(d.ny, dp.f_Ny) || !radix_plan(d.nz, dp.f_Nz))
+    return PAT_ERR_UNSUPPORTED;
+
+  dp.kxu = 2.0 * M_PI / d.lx;
+  dp.kyu = 2.0 * M_PI / d.ly;
+  dp.kzu = 2.0 * M_PI / d.lz;
+  dp.two_c = 2.0 * d.c;
+  dp.s_per_k = d.c * d.dt * dp.n_t / (2.0 * M_PI);
+  dp.n0_over_nt = double(dp.n0) / double(dp.n_t);
+  dp.inv_vol = 1.0 / (d.lx * d.ly * d.lz);
+  // band of oversampled temporal bins read by the interpolation (one bin of margin each side)
+  {
+    const double jx = d.nx / 2 - 1, jy = d.ny / 2 - 1, jz = d.nz / 2 - 1;
+    const double Kx = jx * dp.kxu, Ky = jy * dp.kyu, Kz = jz * dp.kzu;
+    const double smax = std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz) * dp.s_per_k;
+    const double smin = dp.kzu * dp.s_per_k;
+    const long blo = (long)std::floor(smin) - dp.w_t / 2;
+    const long bhi = (long)std::floor(smax) + dp.w_t / 2 + 1;
+    if (bhi - blo + 1 > dp.n_t) return PAT_ERR_UNSUPPORTED;
+    dp.b_lo = (int)blo;
+    dp.nb = (int)(bhi - blo + 1);
+  }
+
+  const pathost::Window wxy(d.kernel == PAT_KERNEL_KAISER_BESSEL ? 1 : 0, d.width_xy, d.sigma_xy);
+  const pathost::Window wt(d.kernel == PAT_KERNEL_KAISER_BESSEL ? 1 : 0, d.width_t, double(dp.n_t) / Nt);
+
+  HostBlob blob;
+  // per-sensor scalar weight h_m * dt
+  std::vector<double> hw(M);
+  for (int m = 0; m < M; ++m) hw[m] = (d.sensor_h ? d.sensor_h[m] : d.lx * d.ly / M) * d.dt;
+  const size_t o_hw = add_real<T>(blob, hw);
+  // temporal deapodisation 1/phihat_t((n - n0)/n_t)
+  std::vector<double> deap(Nt);
+  for (int n = 0; n < Nt; ++n) deap[n] = 1.0 / wt.phihat(double(n - dp.n0) / dp.n_t);
+  const size_t o_deap = add_real<T>(blob, deap);
+  // sensor footprints and weights on the oversampled lateral grid
+  const int w = dp.w_xy;
+  std::vector<int> sbx(M), sby(M);
+  std::vector<double> swx(size_t(M) * w), swy(size_t(M) * w);
+  for (int m = 0; m < M; ++m) {
+    const double ux = (d.sensor_xy[2 * m] + 0.5 * d.lx) * dp.n_x / d.lx;
+    const double uy = (d.sensor_xy[2 * m + 1] + 0.5 * d.ly) * dp.n_y / d.ly;
+    const long fx = (long)std::floor(ux), fy = (long)std::floor(uy);
+    const long bx = fx - w / 2 + 1, by = fy - w / 2 + 1;
+    for (int t = 0; t < w; ++t) {
+      swx[size_t(m) * w + t] = wxy.phi(ux - double(bx + t));
+      swy[size_t(m) * w + t] = wxy.phi(uy - double(by + t));
+    }
+    sbx[m] = (int)(((bx % dp.n_x) + dp.n_x) % dp.n_x);
+    sby[m] = (int)(((by % dp.n_y) + dp.n_y) % dp.n_y);
+  }
+  const size_t o_sbx = blob.add(sbx.data(), sbx.size() * sizeof(int));
+  const size_t o_sby = blob.add(sby.data(), sby.size() * sizeof(int));
+  const size_t o_swx = add_real<T>(blob, swx);
+  const size_t o_swy = add_real<T>(blob, swy);
+  // tile lists: sensors whose (periodic) footprint meets each 16x16 tile, in sensor order
+  const int TS = patk::kSpreadTile;
+  dp.tiles_x = (dp.n_x + TS - 1) / TS;
+  dp.tiles_y = (dp.n_y + TS - 1) / TS;
+  const int ntiles = dp.tiles_x * dp.tiles_y;
+  std::vector<int> cnt(ntiles + 1, 0);
+  std::vector<std::pair<int, int>> inc;
+  inc.reserve(size_t(M) * 4);
+  for (int m = 0; m < M; ++m) {
+    int txs[4], tys[4], ntx = 0, nty = 0;
+    for (int t = 0; t < w; ++t) {
+      const int tx = ((sbx[m] + t) % dp.n_x) / TS;
+      if (std::find(txs, txs + ntx, tx) == txs + ntx) txs[ntx++] = tx;
+      const int ty = ((sby[m] + t) % dp.n_y) / TS;
+      if (std::find(tys, tys + nty, ty) == tys + nty) tys[nty++] = ty;
+      if (ntx > 3 || nty > 3) break;
+    }
+    for (int a = 0; a < ntx; ++a)
+      for (int b = 0; b < nty; ++b) inc.emplace_back(tys[b] * dp.tiles_x + txs[a], m);
+  }
+  for (auto& e : inc) cnt[e.first + 1]++;
+  for (int i = 0; i < ntiles; ++i) cnt[i + 1] += cnt[i];
+  std::vector<int> sens(inc.size());
+  {
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    for (auto& e : inc) sens[pos[e.first]++] = e.second;  // stable: sensors ascending per tile
+  }
+  P->spread_pairs = (int64_t)inc.size();
+  const size_t o_toff = blob.add(cnt.data(), cnt.size() * sizeof(int));
+  const size_t o_tsens = blob.add(sens.data(), std::max<size_t>(1, sens.size()) * sizeof(int));
+  // lateral deconvolution 1/phihat(j/n), zero on the Nyquist mode j = -N/2
+  std::vector<double> dcx(d.nx), dcy(d.ny);
+  for (int jj = 0; jj < d.nx; ++jj) {
+    const int j = jj < d.nx / 2 ? jj : jj - d.nx;
+    dcx[jj] = (jj == d.nx / 2) ? 0.0 : 1.0 / wxy.phihat(double(j) / dp.n_x);
+  }
+  for (int kk = 0; kk < d.ny; ++kk) {
+    const int k = kk < d.ny / 2 ? kk : kk - d.ny;
+    dcy[kk] = (kk == d.ny / 2) ? 0.0 : 1.0 / wxy.phihat(double(k) / dp.n_y);
+  }
+  const size_t o_dcx = add_real<T>(blob, dcx);
+  const size_t o_dcy = add_real<T>(blob, dcy);
+  // temporal tap polynomials
+  std::vector<double> coef;
+  const double tol = sizeof(T) == 8 ? 1e-13 : 1e-9;
+  int deg = 6;
+  for (; deg <= 24; ++deg)
+    if (pathost::fit_tap_polynomials(wt, deg, coef) <= tol) break;
+  if (deg > 24) deg = 24;
+  dp.hdeg = deg;
+  const size_t o_hc = add_real<T>(blob, coef);
+  // twiddles
+  const size_t o_tw_nt = add_twiddles<T>(blob, dp.n_t);
+  const size_t o_tw_nx = add_twiddles<T>(blob, dp.n_x);
+  const size_t o_tw_ny = add_twiddles<T>(blob, dp.n_y);
+  const size_t o_tw_Nx = add_twiddles<T>(blob, d.nx);
+  const size_t o_tw_Ny = add_twiddles<T>(blob, d.ny);
+  const size_t o_tw_Nz = add_twiddles<T>(blob, d.nz);
+
+  P->dev_bytes = align_up(blob.bytes.size());
+  P->dev = dev_alloc(d, P->dev_bytes);
+  if (!P->dev) return PAT_ERR_ALLOC;
+  if (hipMemcpyAsync(P->dev, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return PAT_ERR_HIP;
+  }
+  auto at = [&](size_t off) { return static_cast<const void*>(static_cast<unsigned char*>(P->dev) + off); };
+  dp.hw = at(o_hw);
+  dp.deap = at(o_deap);
+  dp.sbx = static_cast<const int*>(at(o_sbx));
+  dp.sby = static_cast<const int*>(at(o_sby));
+  dp.swx = at(o_swx);
+  dp.swy = at(o_swy);
+  dp.tile_off = static_cast<const int*>(at(o_toff));
+  dp.tile_sens = static_cast<const int*>(at(o_tsens));
+  dp.dcx = at(o_dcx);
+  dp.dcy = at(o_dcy);
+  dp.hcoef = at(o_hc);
+  dp.f_nt.tw = at(o_tw_nt);
+  dp.f_nx.tw = at(o_tw_nx);
+  dp.f_ny.tw = at(o_tw_ny);
+  dp.f_Nx.tw = at(o_tw_Nx);
+  dp.f_Ny.tw = at(o_tw_Ny);
+  dp.f_Nz.tw = at(o_tw_Nz);
+
+  // workspace: region A = grid U (later the lateral spectra Gh);
+  // region B = per-sensor bins Gt, then rows V, then the spectrum F.
+  const size_t c = cxb;
+  const size_t sz_Gt = size_t(M) * dp.nb * c;
+  const size_t sz_U = size_t(dp.nb) * dp.n_y * dp.n_x * c;
+  const size_t sz_V = size_t(dp.nb) * d.nx * dp.n_y * c;
+  const size_t sz_Gh = size_t(d.nx) * d.ny * dp.nb * c;
+  const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
+  const size_t szA = align_up(std::max(sz_U, sz_Gh));
+  const size_t szB = align_up(std::max(sz_Gt, std::max(sz_V, sz_F)));
+  P->off_B = szA;
+  P->ws_bytes = szA + szB;
+  return PAT_OK;
+}
+
+pat_status to_status(hipError_t e) { return e == hipSuccess ? PAT_OK : PAT_ERR_HIP; }
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      prev = -1;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline void mark(pat_plan* P, int call, int stage, hipStream_t s) {
+  if (call >= 0) (void)hipEventRecord(P->ev[size_t(call) * (PAT_TIMING_STAGES + 1) + stage], s);
+}
+
+template <typename T>
+pat_status run(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, bool spectrum_only) {
+  const patk::DevPlan& dp = P->dp;
+  unsigned char* A = static_cast<unsigned char*>(ws);
+  unsigned char* B = A + P->off_B;
+  int call = -1;
+  if (P->ev_used < P->ev_max) call = P->ev_used++;
+  hipError_t e;
+  mark(P, call, 0, s);
+  if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), B, s)) != hipSuccess) return to_status(e);
+  mark(P, call, 1, s);
+  if ((e = patk::launch_spread<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
+  mark(P, call, 2, s);
+  if ((e = patk::launch_fft_x<T>(dp, A, B, s)) != hipSuccess) return to_status(e);
+  mark(P, call, 3, s);
+  if ((e = patk::launch_fft_y<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
+  mark(P, call, 4, s);
+  if (spectrum_only) {
+    if ((e = patk::launch_gather<T>(dp, A, out, true, s)) != hipSuccess) return to_status(e);
+    mark(P, call, 5, s);
+    mark(P, call, 6, s);
+    return PAT_OK;
+  }
+  if ((e = patk::launch_gather<T>(dp, A, B, false, s)) != hipSuccess) return to_status(e);
+  mark(P, call, 5, s);
+  if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s)) != hipSuccess) return to_status(e);
+  mark(P, call, 6, s);
+  return PAT_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const unsigned char* pa = static_cast<const unsigned char*>(a);
+  const unsigned char* pb = static_cast<const unsigned char*>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+
+pat_status compute(pat_plan* P, const void* g, void* out, void* ws, void* stream, bool spectrum_only) {
+  if (!P || !g || !out || !ws) return PAT_ERR_INVALID_ARGUMENT;
+  if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return PAT_ERR_INVALID_ARGUMENT;
+  const size_t eb = P->fp64 ? 8 : 4;
+  const size_t g_bytes = size_t(P->d.n_sensors) * P->d.n_t * eb;
+  const size_t o_bytes = spectrum_only ? size_t(P->d.nx) * P->d.ny * (P->d.nz / 2 + 1) * 2 * eb
+                                       : size_t(P->d.nx) * P->d.ny * P->d.nz * eb;
+  if (overlaps(g, g_bytes, out, o_bytes) || overlaps(g, g_bytes, ws, P->ws_bytes) ||
+      overlaps(out, o_bytes, ws, P->ws_bytes))
+    return PAT_ERR_INVALID_ARGUMENT;
+  DeviceGuard guard(P->device);
+  if (!guard.ok) return PAT_ERR_HIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return P->fp64 ? run<double>(P, g, out, ws, s, spectrum_only) : run<float>(P, g, out, ws, s, spectrum_only);
+}
+
+void destroy_events(pat_plan* P) {
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  P->ev.clear();
+  P->ev_max = 0;
+  P->ev_used = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+pat_status pat_plan_desc_init(pat_plan_desc* d) {
+  if (!d) return PAT_ERR_INVALID_ARGUMENT;
+  std::memset(d, 0, sizeof(*d));
+  d->sigma_xy = 2.0;
+  d->width_xy = 8;
+  d->sigma_t = 2.0;
+  d->width_t = 8;
+  d->kernel = PAT_KERNEL_KAISER_BESSEL;
+  d->precision = PAT_FP32;
+  return PAT_OK;
+}
+
+pat_status nufft_plan(const pat_plan_desc* desc, void* stream, pat_plan** out) {
+  if (!out) return PAT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  pat_status st = validate(desc);
+  if (st != PAT_OK) return st;
+  pat_plan* P = new (std::nothrow) pat_plan();
+  if (!P) return PAT_ERR_ALLOC;
+  P->d = *desc;
+  P->fp64 = desc->precision == PAT_FP64;
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete P;
+    return PAT_ERR_HIP;
+  }
+  st = P->fp64 ? build_tables<double>(P, static_cast<hipStream_t>(stream))
+               : build_tables<float>(P, static_cast<hipStream_t>(stream));
+  P->d.sensor_xy = nullptr;  // host arrays were copied into the tables
+  P->d.sensor_h = nullptr;
+  if (st != PAT_OK) {
+    dev_free(P->d, P->dev);
+    delete P;
+    return st;
+  }
+  *out = P;
+  return PAT_OK;
+}
+
+pat_status nufft_plan_workspace_size(const pat_plan* P, size_t* bytes) {
+  if (!P || !bytes) return PAT_ERR_INVALID_ARGUMENT;
+  *bytes = P->ws_bytes;
+  return PAT_OK;
+}
+
+pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
+  if (!P || !info) return PAT_ERR_INVALID_ARGUMENT;
+  std::memset(info, 0, sizeof(*info));
+  info->nx_over = P->dp.n_x;
+  info->ny_over = P->dp.n_y;
+  info->nt_over = P->dp.n_t;
+  info->band_lo = P->dp.b_lo;
+  info->band_bins = P->dp.nb;
+  info->time_origin = P->dp.n0;
+  info->element_bytes = P->fp64 ? 8 : 4;
+  info->spread_tiles = P->dp.tiles_x * P->dp.tiles_y;
+  info->spread_pairs = P->spread_pairs;
+  info->workspace_bytes = P->ws_bytes;
+  info->table_bytes = P->dev_bytes;
+  return PAT_OK;
+}
+
+pat_status nufft_plan_destroy(pat_plan* P) {
+  if (!P) return PAT_OK;
+  DeviceGuard guard(P->device);
+  (void)hipDeviceSynchronize();
+  destroy_events(P);
+  dev_free(P->d, P->dev);
+  delete P;
+  return PAT_OK;
+}
+
+pat_status pat_reconstruct(pat_plan* P, const void* g, void* f, void* ws, void* stream) {
+  return compute(P, g, f, ws, stream, false);
+}
+
+pat_status pat_spectrum(pat_plan* P, const void* g, void* fhat, void* ws, void* stream) {
+  return compute(P, g, fhat, ws, stream, true);
+}
+
+pat_status pat_forward(pat_plan* P, const void* f, void* g, void* ws, void* stream) {
+  (void)f;
+  (void)g;
+  (void)ws;
+  (void)stream;
+  return P ? PAT_ERR_NOT_IMPLEMENTED : PAT_ERR_INVALID_ARGUMENT;
+}
+
+pat_status pat_adjoint(pat_plan* P, const void* g, void* f, void* ws, void* stream) {
+  (void)f;
+  (void)g;
+  (void)ws;
+  (void)stream;
+  return P ? PAT_ERR_NOT_IMPLEMENTED : PAT_ERR_INVALID_ARGUMENT;
+}
+
+pat_status pat_timing_begin(pat_plan* P, int32_t max_calls) {
+  if (!P || max_calls < 1 || max_calls > 100000) return PAT_ERR_INVALID_ARGUMENT;
+  DeviceGuard guard(P->device);
+  destroy_events(P);
+  const size_t n = size_t(max_calls) * (PAT_TIMING_STAGES + 1);
+  P->ev.resize(n);
+  for (size_t i = 0; i < n; ++i) {
+    if (hipEventCreate(&P->ev[i]) != hipSuccess) {
+      P->ev.resize(i);
+      destroy_events(P);
+      return PAT_ERR_HIP;
+    }
+  }
+  P->ev_max = max_calls;
+  P->ev_used = 0;
+  return PAT_OK;
+}
+
+pat_status pat_timing_end(pat_plan* P, double* ms, int32_t nstage, int32_t* calls) {
+  if (!P || (!ms && nstage > 0) || nstage < 0 || nstage > PAT_TIMING_STAGES) return PAT_ERR_INVALID_ARGUMENT;
+  DeviceGuard guard(P->device);
+  for (int i = 0; i < nstage; ++i) ms[i] = 0.0;
+  pat_status st = PAT_OK;
+  if (P->ev_used > 0) {
+    const size_t last = size_t(P->ev_used) * (PAT_TIMING_STAGES + 1) - 1;
+    if (hipEventSynchronize(P->ev[last]) != hipSuccess) st = PAT_ERR_HIP;
+    for (int c = 0; c < P->ev_used && st == PAT_OK; ++c)
+      for (int k = 0; k < nstage; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, P->ev[size_t(c) * (PAT_TIMING_STAGES + 1) + k],
+                                P->ev[size_t(c) * (PAT_TIMING_STAGES + 1) + k + 1]) != hipSuccess) {
+          st = PAT_ERR_HIP;
+          break;
+        }
+        ms[k] += t;
+      }
+  }
+  if (calls) *calls = P->ev_used;
+  destroy_events(P);
+  return st;
+}
+
+const char* pat_status_str(pat_status s) {
+  switch (s) {
+    case PAT_OK: return "PAT_OK";
+    case PAT_ERR_INVALID_ARGUMENT: return "PAT_ERR_INVALID_ARGUMENT: invalid argument";
+    case PAT_ERR_UNSUPPORTED: return "PAT_ERR_UNSUPPORTED: size or parameter not supported";
+    case PAT_ERR_ALLOC: return "PAT_ERR_ALLOC: device allocation failed";
+    case PAT_ERR_HIP: return "PAT_ERR_HIP: HIP runtime error";
+    case PAT_ERR_NOT_IMPLEMENTED: return "PAT_ERR_NOT_IMPLEMENTED: not implemented";
+  }
+  return "unknown pat_status";
+}
+
+const char* pat_version(void) { return "patnufft 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,522 @@
+// gfx950 kernels of the NEDNER-NUFFT reconstruction (Section 3: a
+// non-equispaced-range NUFFT in time, a non-equispaced-data NUFFT over the
+// sensor plane, then an equispaced inverse FFT).
+//
+// Order of the steps on the device. The temporal transform's equispaced part
+// (deapodise, zero-pad, FFT) runs first, per sensor; the lateral NUFFT then
+// runs once per kept temporal bin; the temporal interpolation at
+// omega(K) = c|K| runs last, per lateral mode. This is the paper's
+// composition with the two linear maps on different indices applied in the
+// other order, which lets the lateral grid be built only for the band of
+// temporal bins that the interpolation reads.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "fft_device.hpp"
+#include "kernels.hpp"
+
+namespace patk {
+
+template <typename T>
+struct MaxV;
+template <>
+struct MaxV<float> {
+  static constexpr int v = 32;
+};
+template <>
+struct MaxV<double> {
+  static constexpr int v = 16;
+};
+
+// Sequences of length n one FFT work-group holds: limited by the register
+// staging (MaxV values per thread) and by 64 KiB of LDS with one pad element
+// per sequence.
+template <typename T>
+static int lds_batch(int n, int cap) {
+  int b = MaxV<T>::v * 256 / n;
+  const int by_lds = int(65536 / (size_t(n + 1) * 2 * sizeof(T)));
+  if (b > by_lds) b = by_lds;
+  if (b > cap) b = cap;
+  return b;
+}
+
+template <typename T>
+static FftDesc<T> as_desc(const FftRaw& r) {
+  FftDesc<T> d;
+  d.n = r.n;
+  d.npass = r.npass;
+  for (int i = 0; i < 16; ++i) d.radix[i] = r.radix[i];
+  d.tw = static_cast<const cx<T>*>(r.tw);
+  return d;
+}
+
+__device__ __forceinline__ int imod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 0: temporal FFT per sensor (the equispaced half of eq. NER_NUFFT).
+// Two real traces share one complex FFT (re = sensor m0, im = sensor m1).
+// Sample n sits at index (n - n0) mod n_t after multiplication by
+// h_m*dt/phihat_t((n - n0)/n_t); bins b_lo .. b_lo+nb-1 are kept per sensor.
+// ---------------------------------------------------------------------------
+constexpr int kTemporalThreads = 512;
+constexpr int kTemporalMaxV = 16;
+
+template <typename T>
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
+                                                             const T* __restrict__ hw, const T* __restrict__ deap,
+                                                             FftDesc<T> fd, int b_lo, int nb,
+                                                             cx<T>* __restrict__ Gt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_t = fd.n;
+  const int m0 = 2 * blockIdx.x;
+  const int m1 = m0 + 1;
+  const bool has1 = m1 < M;
+  for (int q = tid; q < n_t; q += nthr) buf[q] = cx<T>{T(0), T(0)};
+  __syncthreads();
+  const T w0 = hw[m0];
+  const T w1 = has1 ? hw[m1] : T(0);
+  const T* g0 = g + size_t(m0) * Nt;
+  const T* g1 = g + size_t(has1 ? m1 : m0) * Nt;
+  for (int n = tid; n < Nt; n += nthr) {
+    const T d = deap[n];
+    const T a = g0[n] * w0 * d;
+    const T b = has1 ? g1[n] * w1 * d : T(0);
+    int pos = n - n0;
+    if (pos < 0) pos += n_t;
+    buf[pos] = cx<T>{a, b};
+  }
+  __syncthreads();
+  fft_lds<T, kTemporalMaxV, false>(buf, fd, 1, n_t, tid, nthr);
+  cx<T>* o0 = Gt + size_t(m0) * nb;
+  cx<T>* o1 = Gt + size_t(m1) * nb;
+  for (int i = tid; i < nb; i += nthr) {
+    const int b = b_lo + i;
+    const cx<T> z = buf[imod(b, n_t)];
+    const cx<T> zm = buf[imod(-b, n_t)];
+    // transform of the real part: (Z_b + conj Z_-b)/2; of the imaginary part: (Z_b - conj Z_-b)/(2i)
+    o0[i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+    if (has1) o1[i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+  }
+}
+
+template <typename T>
+hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s) {
+  const int blocks = (p.M + 1) / 2;
+  const size_t lds = size_t(p.n_t) * sizeof(cx<T>);
+  hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
+                     static_cast<const T*>(p.hw), static_cast<const T*>(p.deap), as_desc<T>(p.f_nt), p.b_lo, p.nb,
+                     static_cast<cx<T>*>(Gt));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1: lateral spreading (the gridding of eq. NED_NUFFT), one temporal
+// bin chunk at a time. Output-driven and atomic-free: a work-group owns a
+// 16x16 tile of the oversampled grid (four waves, each a 16x4 patch), and
+// every lane owns one grid point, accumulating in registers the
+// contributions of the tile's sensor list in list order (deterministic).
+// The sensor's bin values are wave-uniform (scalar loads); its weight at the
+// lane's point is wx[tx]*wy[ty] (0 outside the footprint).
+// ---------------------------------------------------------------------------
+constexpr int kSpreadBins = 16;
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
+                                                const int* __restrict__ tile_sens, const int* __restrict__ sbx,
+                                                const int* __restrict__ sby, const T* __restrict__ swx,
+                                                const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
+                                                int nchunks, cx<T>* __restrict__ U) {
+  constexpr int BC = kSpreadBins;
+  const int chunk = blockIdx.x % nchunks;
+  const int tile = blockIdx.x / nchunks;
+  const int tyi = tile / tiles_x;
+  const int txi = tile - tyi * tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int px = txi * kSpreadTile + (lane & 15);
+  const int prow0 = tyi * kSpreadTile + wave * 4;
+  const int py = prow0 + (lane >> 4);
+  const int b0 = chunk * BC;
+  const int nbc = min(BC, nb - b0);
+  cx<T> acc[BC];
+  cx<T> cmp[KAHAN ? BC : 1];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) acc[b] = cx<T>{T(0), T(0)};
+  if (KAHAN) {
+#pragma unroll
+    for (int b = 0; b < (KAHAN ? BC : 1); ++b) cmp[b] = cx<T>{T(0), T(0)};
+  }
+  const int q_begin = tile_off[tile];
+  const int q_end = tile_off[tile + 1];
+  for (int q = q_begin; q < q_end; ++q) {
+    const int sidx = tile_sens[q];
+    const int by = sby[sidx];
+    int d0 = prow0 - by;
+    if (d0 < 0) d0 += n_y;
+    if (!(d0 < w || d0 + 3 >= n_y)) continue;  // footprint misses this wave's four rows
+    const int bx = sbx[sidx];
+    int tx = px - bx;
+    if (tx < 0) tx += n_x;
+    int ty = py - by;
+    if (ty < 0) ty += n_y;
+    T wt = T(0);
+    if (tx < w && ty < w) wt = swx[sidx * w + tx] * swy[sidx * w + ty];
+    const cx<T>* gs = Gt + size_t(sidx) * nb + b0;
+    if (nbc == BC) {
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        const cx<T> gv = gs[b];
+        if (KAHAN) {
+          T yr = wt * gv.x - cmp[b].x;
+          T tr = acc[b].x + yr;
+          cmp[b].x = (tr - acc[b].x) - yr;
+          acc[b].x = tr;
+          T yi = wt * gv.y - cmp[b].y;
+          T ti = acc[b].y + yi;
+          cmp[b].y = (ti - acc[b].y) - yi;
+          acc[b].y = ti;
+        } else {
+          acc[b].x += wt * gv.x;
+          acc[b].y += wt * gv.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < BC; ++b) {
+        if (b < nbc) {
+          const cx<T> gv = gs[b];
+          if (KAHAN) {
+            T yr = wt * gv.x - cmp[b].x;
+            T tr = acc[b].x + yr;
+            cmp[b].x = (tr - acc[b].x) - yr;
+            acc[b].x = tr;
+            T yi = wt * gv.y - cmp[b].y;
+            T ti = acc[b].y + yi;
+            cmp[b].y = (ti - acc[b].y) - yi;
+            acc[b].y = ti;
+          } else {
+            acc[b].x += wt * gv.x;
+            acc[b].y += wt * gv.y;
+          }
+        }
+      }
+    }
+  }
+  if (px < n_x && py < n_y) {
+    cx<T>* out = U + (size_t(b0) * n_y + py) * n_x + px;
+    const size_t slice = size_t(n_y) * n_x;
+#pragma unroll
+    for (int b = 0; b < BC; ++b)
+      if (b < nbc) out[b * slice] = acc[b];
+  }
+}
+
+template <typename T>
+hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t s) {
+  const int nchunks = (p.nb + kSpreadBins - 1) / kSpreadBins;
+  const long long blocks = (long long)p.tiles_x * p.tiles_y * nchunks;
+  if (p.kahan)
+    hipLaunchKernelGGL((k_spread<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt), p.nb,
+                       p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks,
+                       static_cast<cx<T>*>(U));
+  else
+    hipLaunchKernelGGL((k_spread<T, false>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt),
+                       p.nb, p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks,
+                       static_cast<cx<T>*>(U));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2: FFT along x of every grid row, keeping the Nx centred modes.
+// U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
+// ---------------------------------------------------------------------------
+constexpr int kFftThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
+                                                     FftDesc<T> fd, cx<T>* __restrict__ V) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_x = fd.n;
+  const int bstride = n_x + 1;
+  const int b = blockIdx.y;
+  const int py0 = blockIdx.x * rows;
+  const int nr = min(rows, n_y - py0);
+  const cx<T>* src = U + (size_t(b) * n_y + py0) * n_x;
+  for (int q = tid; q < nr * n_x; q += nthr) {
+    const int r = q / n_x;
+    const int px = q - r * n_x;
+    buf[r * bstride + px] = src[q];
+  }
+  __syncthreads();
+  fft_lds<T, MaxV<T>::v, false>(buf, fd, nr, bstride, tid, nthr);
+  cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
+  for (int q = tid; q < nr * Nx; q += nthr) {
+    const int jj = q / nr;
+    const int r = q - jj * nr;
+    const int j = jj < Nx / 2 ? jj : jj - Nx;
+    dst[size_t(jj) * n_y + r] = buf[r * bstride + (j < 0 ? j + n_x : j)];
+  }
+}
+
+template <typename T>
+hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, hipStream_t s) {
+  const int rows = lds_batch<T>(p.n_x, 16);
+  if (rows < 1) return hipErrorInvalidValue;
+  const size_t lds = size_t(rows) * (p.n_x + 1) * sizeof(cx<T>);
+  dim3 grid((p.n_y + rows - 1) / rows, p.nb);
+  hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
+                     as_desc<T>(p.f_nx), static_cast<cx<T>*>(V));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3: FFT along y, keep the Ny centred modes, divide by the window
+// transform in x and y (eq. NED_NUFFT's 1/Psi_j), and transpose so the bins
+// of each lateral mode are contiguous: V[b][jj][py] -> Gh[jj][kk][b].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
+                                                     const T* __restrict__ dcx, const T* __restrict__ dcy,
+                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_y = fd.n;
+  const int bstride = n_y + 1;
+  const int jj = blockIdx.y;
+  const int b0 = blockIdx.x * bins;
+  const int nbc = min(bins, nb - b0);
+  for (int q = tid; q < nbc * n_y; q += nthr) {
+    const int bi = q / n_y;
+    const int py = q - bi * n_y;
+    buf[bi * bstride + py] = V[(size_t(b0 + bi) * Nx + jj) * n_y + py];
+  }
+  __syncthreads();
+  fft_lds<T, MaxV<T>::v, false>(buf, fd, nbc, bstride, tid, nthr);
+  const T cxj = dcx[jj];
+  cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
+  for (int q = tid; q < nbc * Ny; q += nthr) {
+    const int kk = q / nbc;
+    const int bi = q - kk * nbc;
+    const int k = kk < Ny / 2 ? kk : kk - Ny;
+    const T sc = cxj * dcy[kk];
+    const cx<T> v = buf[bi * bstride + (k < 0 ? k + n_y : k)];
+    dst[size_t(kk) * nb + bi] = cx<T>{v.x * sc, v.y * sc};
+  }
+}
+
+template <typename T>
+hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
+  const int bins = lds_batch<T>(p.n_y, 16);
+  if (bins < 1) return hipErrorInvalidValue;
+  const size_t lds = size_t(bins) * (p.n_y + 1) * sizeof(cx<T>);
+  dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+  hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
+                     bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
+                     static_cast<cx<T>*>(Gh));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 4: temporal interpolation at omega(K) (the window sum of
+// eq. NER_NUFFT with the centring phase of eq. PSI) and the inversion
+// weight of eq. exact. For lateral mode (j,k) and l = 1..Nz/2-1:
+//   s  = c |K| dt n_t / (2 pi)                  (double)
+//   S  = exp(-2 pi i s n0/n_t) sum_t phi_t(s - b_t) Gh[j][k][b_t]
+//   F  = 2c Kz/|K| * S
+// The l = 0, l = Nz/2, j = -Nx/2 and k = -Ny/2 entries are written as 0.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                                double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                                double n0_over_nt, double scale, int physical, int wt, int deg,
+                                                const T* __restrict__ hcoef, cx<T>* __restrict__ Fh) {
+  const int Lh = Nz / 2 + 1;
+  const long long total = (long long)Nx * Ny * Lh;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int l = int(idx % Lh);
+  const long long col = idx / Lh;
+  const int kk = int(col % Ny);
+  const int jj = int(col / Ny);
+  if (l == 0 || l == Nz / 2 || jj == Nx / 2 || kk == Ny / 2) {
+    Fh[idx] = cx<T>{T(0), T(0)};
+    return;
+  }
+  const int j = jj < Nx / 2 ? jj : jj - Nx;
+  const int k = kk < Ny / 2 ? kk : kk - Ny;
+  const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
+  const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+  const double s = Kabs * s_per_k;
+  const double fl = floor(s);
+  const T y = T(2.0 * (s - fl) - 1.0);
+  int base = int(fl) - wt / 2 + 1 - b_lo;
+  base = base < 0 ? 0 : (base > nb - wt ? nb - wt : base);
+  const cx<T>* src = Gh + col * nb + base;
+  cx<T> acc{T(0), T(0)};
+  const int np = deg + 1;
+  for (int t = 0; t < wt; ++t) {
+    const T* c = hcoef + t * np;
+    T v = c[deg];
+    for (int d = deg - 1; d >= 0; --d) v = v * y + c[d];
+    const cx<T> gv = src[t];
+    acc.x += v * gv.x;
+    acc.y += v * gv.y;
+  }
+  double q = s * n0_over_nt;
+  q -= floor(q);
+  double sn, cs;
+  sincos(-2.0 * M_PI * q, &sn, &cs);
+  double wgt = two_c * Kz / Kabs * scale;
+  if (physical && ((jj + kk) & 1)) wgt = -wgt;
+  const cx<T> ph{T(wgt * cs), T(wgt * sn)};
+  Fh[idx] = cmul(acc, ph);
+}
+
+template <typename T>
+hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, bool physical, hipStream_t s) {
+  const long long total = (long long)p.Nx * p.Ny * (p.Nz / 2 + 1);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  const double scale = physical ? 1.0 : p.inv_vol;
+  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gh), p.nb, p.b_lo, p.Nx,
+                     p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, scale, physical ? 1 : 0,
+                     p.w_t, p.hdeg, static_cast<const T*>(p.hcoef), static_cast<cx<T>*>(Fh));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 5: equispaced inverse 3-D FFT (step 3 of the NEDNER list) on the
+// half spectrum Fh[jj][kk][l], l = 0..Nz/2: in-place inverse transforms
+// along x and along y, then a complex-to-real transform along z.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
+                                                      FftDesc<T> fd) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Nx = fd.n;
+  const int bstride = Nx + 1;
+  const int kk = blockIdx.y;
+  const int l0 = blockIdx.x * lchunk;
+  const int nl = min(lchunk, Lh - l0);
+  for (int q = tid; q < nl * Nx; q += nthr) {
+    const int jj = q / nl;
+    const int li = q - jj * nl;
+    buf[li * bstride + jj] = F[(size_t(jj) * Ny + kk) * Lh + l0 + li];
+  }
+  __syncthreads();
+  fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
+  for (int q = tid; q < nl * Nx; q += nthr) {
+    const int jj = q / nl;
+    const int li = q - jj * nl;
+    F[(size_t(jj) * Ny + kk) * Lh + l0 + li] = buf[li * bstride + jj];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Ny = fd.n;
+  const int bstride = Ny + 1;
+  const int jj = blockIdx.y;
+  const int l0 = blockIdx.x * lchunk;
+  const int nl = min(lchunk, Lh - l0);
+  cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
+  for (int q = tid; q < nl * Ny; q += nthr) {
+    const int kk = q / nl;
+    const int li = q - kk * nl;
+    buf[li * bstride + kk] = base[size_t(kk) * Lh + li];
+  }
+  __syncthreads();
+  fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
+  for (int q = tid; q < nl * Ny; q += nthr) {
+    const int kk = q / nl;
+    const int li = q - kk * nl;
+    base[size_t(kk) * Lh + li] = buf[li * bstride + kk];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
+                                                     FftDesc<T> fd, T* __restrict__ f) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Nz = fd.n;
+  const int Lh = Nz / 2 + 1;
+  const int bstride = Nz + 1;
+  const long long r0 = (long long)blockIdx.x * rows;
+  const int nr = (int)min((long long)rows, nrows - r0);
+  for (int q = tid; q < nr * Lh; q += nthr) {
+    const int r = q / Lh;
+    const int l = q - r * Lh;
+    const cx<T> v = F[(r0 + r) * Lh + l];
+    buf[r * bstride + l] = v;
+    if (l > 0 && l < Nz / 2) buf[r * bstride + Nz - l] = cx<T>{v.x, -v.y};
+  }
+  __syncthreads();
+  fft_lds<T, MaxV<T>::v, true>(buf, fd, nr, bstride, tid, nthr);
+  for (int q = tid; q < nr * Nz; q += nthr) {
+    const int r = q / Nz;
+    const int e = q - r * Nz;
+    f[(r0 + r) * Nz + e] = buf[r * bstride + e].x;
+  }
+}
+
+template <typename T>
+hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
+  cx<T>* F = static_cast<cx<T>*>(Fh);
+  const int Lh = p.Nz / 2 + 1;
+  {
+    const int lc = lds_batch<T>(p.Nx, 16);
+    if (lc < 1) return hipErrorInvalidValue;
+    dim3 grid((Lh + lc - 1) / lc, p.Ny);
+    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(kFftThreads), size_t(lc) * (p.Nx + 1) * sizeof(cx<T>), s, F, p.Ny, Lh,
+                       lc, as_desc<T>(p.f_Nx));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int lc = lds_batch<T>(p.Ny, 16);
+    if (lc < 1) return hipErrorInvalidValue;
+    dim3 grid((Lh + lc - 1) / lc, p.Nx);
+    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(kFftThreads), size_t(lc) * (p.Ny + 1) * sizeof(cx<T>), s, F, Lh, lc,
+                       as_desc<T>(p.f_Ny));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int rows = lds_batch<T>(p.Nz, 16);
+    if (rows < 1) return hipErrorInvalidValue;
+    const long long nrows = (long long)p.Nx * p.Ny;
+    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(kFftThreads),
+                       size_t(rows) * (p.Nz + 1) * sizeof(cx<T>), s, F, nrows, rows, as_desc<T>(p.f_Nz), f);
+  }
+  return hipGetLastError();
+}
+
+#define PATK_INSTANTIATE(T)                                                                     \
+  template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, hipStream_t);         \
+  template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, hipStream_t);         \
+  template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, hipStream_t);         \
+  template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);         \
+  template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, bool, hipStream_t);  \
+  template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t);
+
+PATK_INSTANTIATE(float)
+PATK_INSTANTIATE(double)
+
+}  // namespace patk

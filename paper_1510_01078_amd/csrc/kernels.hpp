@@ -1,0 +1,61 @@
+// Interface between the host plan code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace patk {
+
+struct FftRaw {
+  int n = 0;
+  int npass = 0;
+  int radix[16] = {0};
+  const void* tw = nullptr;  // device, n complex entries exp(-2 pi i t/n)
+};
+
+// Everything a launch needs, as plain values and device pointers.
+struct DevPlan {
+  int M = 0, Nt = 0, Nx = 0, Ny = 0, Nz = 0;
+  int n_x = 0, n_y = 0, n_t = 0, n0 = 0, b_lo = 0, nb = 0;
+  int w_xy = 0, w_t = 0, hdeg = 0;
+  int tiles_x = 0, tiles_y = 0;
+  bool kahan = false;
+  double s_per_k = 0.0;        // c*dt*n_t/(2 pi): oversampled bin per unit |K|
+  double kxu = 0, kyu = 0, kzu = 0;  // 2 pi/X, 2 pi/Y, 2 pi/Z
+  double two_c = 0.0;          // 2c of W(K) = 2c|Kz|/|K|
+  double n0_over_nt = 0.0;     // centring phase factor n0/n_t
+  double inv_vol = 0.0;        // 1/(XYZ)
+  // device tables (element type T unless int)
+  const void* hw = nullptr;       // [M]   h_m*dt
+  const void* deap = nullptr;     // [Nt]  1/phihat_t((n - n0)/n_t)
+  const int* sbx = nullptr;       // [M]   first x grid point of the footprint (mod n_x)
+  const int* sby = nullptr;       // [M]
+  const void* swx = nullptr;      // [M][w] x weights
+  const void* swy = nullptr;      // [M][w]
+  const int* tile_off = nullptr;  // [tiles+1]
+  const int* tile_sens = nullptr; // sensors whose footprint meets each tile
+  const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
+  const void* dcy = nullptr;      // [Ny]
+  const void* hcoef = nullptr;    // [w_t][hdeg+1] temporal tap polynomials
+  FftRaw f_nt, f_nx, f_ny, f_Nx, f_Ny, f_Nz;
+};
+
+constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
+
+// Stage launchers; T = float or double. Buffers are device pointers.
+template <typename T>
+hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s);
+template <typename T>
+hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t s);
+template <typename T>
+hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, hipStream_t s);
+template <typename T>
+hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s);
+// physical = true: F(K) as defined (sign (-1)^(j+k), no 1/V); false: the
+// image-ready spectrum (-1)^(j+k) F(K) / (XYZ) consumed by launch_inverse.
+template <typename T>
+hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, bool physical, hipStream_t s);
+template <typename T>
+hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s);
+
+}  // namespace patk

@@ -185,6 +185,26 @@ class Balls:
         return len(self.radii)
 
 
+def _ball_traces_part(xy, balls, idx, nt, dt, c):
+    m = xy.shape[0]
+    g = np.zeros((m, nt), dtype=np.float64)
+    rows = np.arange(m)
+    for b in idx:
+        cx, cy, cz = balls.centres[b]
+        R = float(balls.radii[b])
+        a = float(balls.p0[b])
+        d = np.sqrt((xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2 + cz * cz)
+        n_lo = np.floor((d - R) / (c * dt)).astype(np.int64)
+        width = int(math.ceil(2.0 * R / (c * dt))) + 3
+        n_idx = n_lo[:, None] + np.arange(width)[None, :]
+        arg = d[:, None] - c * (n_idx * dt)
+        inside = (np.abs(arg) < R) & (n_idx >= 0) & (n_idx < nt)
+        ii = np.broadcast_to(rows[:, None], n_idx.shape)[inside]
+        nn = n_idx[inside]
+        g[ii, nn] += (a * arg / (2.0 * d[:, None]))[inside]  # (m, n) pairs are distinct within one ball
+    return g
+
+
 def ball_traces(xy: np.ndarray, balls: Balls, nt: int, dt: float, c: float = C_SOUND,
                 dtype=np.float64) -> np.ndarray:
     """Pressure traces on z = 0 from uniform balls (3-D wave equation, free space).
@@ -193,25 +213,25 @@ def ball_traces(xy: np.ndarray, balls: Balls, nt: int, dt: float, c: float = C_S
     centre, the pressure is the N-shaped p0*(d - c*t)/(2*d) while |d - c*t| < R
     and 0 otherwise (strict inequality, point samples, no filter). Traces of
     several balls add. Returns g [M, nt].
+
+    Many balls are split into a fixed number of contiguous groups summed on
+    worker threads, then added in group order, so the result does not depend
+    on the machine's core count.
     """
-    m = xy.shape[0]
-    g = np.zeros((m, nt), dtype=np.float64)
-    rows = np.arange(m)
-    for b in range(len(balls)):
-        cx, cy, cz = balls.centres[b]
-        R = float(balls.radii[b])
-        a = float(balls.p0[b])
-        d = np.sqrt((xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2 + cz * cz)
-        n_lo = np.floor((d - R) / (c * dt)).astype(np.int64)
-        width = int(math.ceil(2.0 * R / (c * dt))) + 3
-        n_idx = n_lo[:, None] + np.arange(width)[None, :]
-        t = n_idx * dt
-        arg = d[:, None] - c * t
-        inside = (np.abs(arg) < R) & (n_idx >= 0) & (n_idx < nt)
-        val = np.where(inside, a * arg / (2.0 * d[:, None]), 0.0)
-        ii = np.broadcast_to(rows[:, None], n_idx.shape)[inside]
-        nn = n_idx[inside]
-        np.add.at(g, (ii, nn), val[inside])
+    xy = np.asarray(xy, dtype=np.float64)
+    nballs = len(balls)
+    groups = 1 if nballs < 64 else 8
+    bounds = np.linspace(0, nballs, groups + 1).astype(int)
+    parts = [range(bounds[i], bounds[i + 1]) for i in range(groups)]
+    if groups == 1:
+        g = _ball_traces_part(xy, balls, parts[0], nt, dt, c)
+    else:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(groups) as ex:
+            res = list(ex.map(lambda ix: _ball_traces_part(xy, balls, ix, nt, dt, c), parts))
+        g = res[0]
+        for r in res[1:]:
+            g += r
     return g.astype(dtype, copy=False)
 
 

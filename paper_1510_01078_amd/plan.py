@@ -1,0 +1,164 @@
+"""Python binding of the NEDNER-NUFFT library (argument marshalling only).
+
+Every step of the reconstruction runs in the HIP kernels of libpatnufft.so;
+this module only builds the plan descriptor, hands PyTorch device memory to
+the library (the plan's tables through an allocator callback, the workspace
+and outputs as tensors) and passes torch's current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+
+_KERNELS = {"gaussian": N.PAT_KERNEL_GAUSSIAN, "kaiser_bessel": N.PAT_KERNEL_KAISER_BESSEL,
+            "kb": N.PAT_KERNEL_KAISER_BESSEL}
+_PRECISIONS = {"fp64": N.PAT_FP64, "fp32": N.PAT_FP32, "fp32_kahan": N.PAT_FP32_KAHAN}
+
+
+class Plan:
+    """A reconstruction plan for one sensor geometry, trace length and grid.
+
+    Parameters mirror pat_plan_desc: sensor_xy [M,2] (metres, plane-centred),
+    sensor_h [M] (m^2, None for X*Y/M), n_t, dt, c, shape (Nx,Ny,Nz),
+    extent (X,Y,Z), lateral/temporal oversampling and window widths, window
+    kernel ('kaiser_bessel' or 'gaussian') and precision ('fp32',
+    'fp32_kahan' or 'fp64'). The plan lives on `device` (default: the
+    current CUDA/HIP device) and uses torch's current stream there.
+    """
+
+    def __init__(self, sensor_xy, n_t, dt, c, shape, extent, sensor_h=None, sigma_xy=2.0, width_xy=8,
+                 sigma_t=2.0, width_t=8, kernel="kaiser_bessel", precision="fp32", device=None):
+        import torch
+
+        self._torch = torch
+        self._lib = N.load()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        if self.device.type != "cuda":
+            raise ValueError("Plan needs a GPU device")
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        xy = np.ascontiguousarray(sensor_xy, dtype=np.float64).reshape(-1, 2)
+        self._xy = xy
+        self._h = None if sensor_h is None else np.ascontiguousarray(sensor_h, dtype=np.float64).reshape(-1)
+        if self._h is not None and self._h.shape[0] != xy.shape[0]:
+            raise ValueError("sensor_h must have one entry per sensor")
+        self.m = xy.shape[0]
+        self.n_t = int(n_t)
+        self.shape = tuple(int(s) for s in shape)
+        self.extent = tuple(float(e) for e in extent)
+
+        d = N.PlanDesc()
+        N.check(self._lib.pat_plan_desc_init(C.byref(d)), "pat_plan_desc_init")
+        d.n_sensors = self.m
+        d.n_t = self.n_t
+        d.dt = float(dt)
+        d.c = float(c)
+        d.sensor_xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+        d.sensor_h = self._h.ctypes.data_as(C.POINTER(C.c_double)) if self._h is not None else None
+        d.nx, d.ny, d.nz = self.shape
+        d.lx, d.ly, d.lz = self.extent
+        d.sigma_xy = float(sigma_xy)
+        d.width_xy = int(width_xy)
+        d.sigma_t = float(sigma_t)
+        d.width_t = int(width_t)
+        d.kernel = _KERNELS[kernel]
+        d.precision = _PRECISIONS[precision]
+
+        self._blocks = {}
+        dev = self.device
+
+        def _alloc(nbytes, ctx):
+            try:
+                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+                p = t.data_ptr()
+                self._blocks[p] = t
+                return p
+            except Exception:  # allocation failure -> NULL -> PAT_ERR_ALLOC
+                return None
+
+        def _free(ptr, ctx):
+            self._blocks.pop(ptr, None)
+
+        self._alloc_cb = N.ALLOC_FN(_alloc)
+        self._free_cb = N.FREE_FN(_free)
+        d.alloc = self._alloc_cb
+        d.free = self._free_cb
+        self._desc = d
+        handle = C.c_void_p()
+        with torch.cuda.device(dev):
+            stream = torch.cuda.current_stream(dev)
+            N.check(self._lib.nufft_plan(C.byref(d), C.c_void_p(stream.cuda_stream), C.byref(handle)), "nufft_plan")
+        self._handle = handle
+        info = N.PlanInfo()
+        N.check(self._lib.pat_plan_get_info(handle, C.byref(info)), "pat_plan_get_info")
+        self.info = {f: getattr(info, f) for f, _ in N.PlanInfo._fields_}
+        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=dev)
+
+    # ------------------------------------------------------------------
+    def _stream(self):
+        return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _check_traces(self, g):
+        torch = self._torch
+        if not isinstance(g, torch.Tensor) or g.device != self.device:
+            raise ValueError(f"traces must be a tensor on {self.device}")
+        if g.dtype != self.dtype or tuple(g.shape) != (self.m, self.n_t) or not g.is_contiguous():
+            raise ValueError(f"traces must be contiguous {self.dtype} of shape {(self.m, self.n_t)}")
+
+    def reconstruct(self, g, out=None, workspace=None):
+        """f = R g (pat_reconstruct). g: [M, Nt] device tensor. Returns [Nx,Ny,Nz]."""
+        self._check_handle()
+        self._check_traces(g)
+        torch = self._torch
+        if out is None:
+            out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
+        elif out.dtype != self.dtype or tuple(out.shape) != self.shape or not out.is_contiguous():
+            raise ValueError("bad output tensor")
+        ws = self.workspace if workspace is None else workspace
+        N.check(self._lib.pat_reconstruct(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          C.c_void_p(ws.data_ptr()), self._stream()), "pat_reconstruct")
+        return out
+
+    def spectrum(self, g, out=None):
+        """F(K) half spectrum [Nx, Ny, Nz/2+1] complex (pat_spectrum)."""
+        self._check_handle()
+        self._check_traces(g)
+        torch = self._torch
+        shp = (self.shape[0], self.shape[1], self.shape[2] // 2 + 1)
+        if out is None:
+            out = torch.empty(shp, dtype=self.cdtype, device=self.device)
+        N.check(self._lib.pat_spectrum(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       C.c_void_p(self.workspace.data_ptr()), self._stream()), "pat_spectrum")
+        return out
+
+    def timing_begin(self, max_calls: int):
+        self._check_handle()
+        N.check(self._lib.pat_timing_begin(self._handle, int(max_calls)), "pat_timing_begin")
+
+    def timing_end(self):
+        """Returns (per-stage summed milliseconds [6], number of calls recorded)."""
+        self._check_handle()
+        ms = (C.c_double * N.PAT_TIMING_STAGES)()
+        calls = C.c_int32()
+        N.check(self._lib.pat_timing_end(self._handle, ms, N.PAT_TIMING_STAGES, C.byref(calls)), "pat_timing_end")
+        return list(ms), calls.value
+
+    def _check_handle(self):
+        if self._handle is None:
+            raise RuntimeError("plan is closed")
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None:
+            self._lib.nufft_plan_destroy(self._handle)
+            self._handle = None
+            self._blocks.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

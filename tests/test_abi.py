@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports every declared symbol; host-side
+argument validation returns the documented status codes (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1510_01078_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "pat_nufft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^(?:pat_status|const char\s*\*)\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_symbols_exported():
+    lib = N.load()
+    names = _declared_functions()
+    assert "nufft_plan" in names and "pat_reconstruct" in names and "pat_forward" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(N.SIGNATURES)
+
+
+def test_status_strings():
+    lib = N.load()
+    for s in range(6):
+        assert lib.pat_status_str(s).decode().startswith("PAT_")
+    assert b"gfx950" in lib.pat_version()
+
+
+def _desc(xy, **kw):
+    lib = N.load()
+    d = N.PlanDesc()
+    assert lib.pat_plan_desc_init(C.byref(d)) == N.PAT_OK
+    d.n_sensors = xy.shape[0]
+    d.n_t = 64
+    d.dt = 25e-9
+    d.c = 1500.0
+    d.sensor_xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+    d.nx = d.ny = d.nz = 16
+    d.lx = d.ly = d.lz = 1e-2
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+@pytest.mark.parametrize("field,value,expect", [
+    ("n_sensors", 0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("n_t", 1, N.PAT_ERR_INVALID_ARGUMENT),
+    ("dt", 0.0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("c", -1.0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("nx", 15, N.PAT_ERR_INVALID_ARGUMENT),
+    ("nz", 2, N.PAT_ERR_INVALID_ARGUMENT),
+    ("lx", 0.0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("sigma_xy", 1.0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("sigma_t", 9.0, N.PAT_ERR_INVALID_ARGUMENT),
+    ("width_xy", 7, N.PAT_ERR_INVALID_ARGUMENT),
+    ("width_t", 18, N.PAT_ERR_UNSUPPORTED),
+    ("width_xy", 20, N.PAT_ERR_UNSUPPORTED),
+    ("kernel", 7, N.PAT_ERR_INVALID_ARGUMENT),
+    ("precision", 9, N.PAT_ERR_INVALID_ARGUMENT),
+])
+def test_descriptor_validation(field, value, expect):
+    lib = N.load()
+    xy = np.zeros((4, 2))
+    d = _desc(xy, **{field: value})
+    h = C.c_void_p(1234)
+    assert lib.nufft_plan(C.byref(d), None, C.byref(h)) == expect
+    assert h.value is None
+
+
+def test_sensor_outside_plane_rejected():
+    lib = N.load()
+    for bad in ([0.005, 0.0], [-0.0050001, 0.0], [0.0, 0.0051], [np.nan, 0.0]):
+        xy = np.array([[0.0, 0.0], bad])
+        d = _desc(xy)
+        h = C.c_void_p()
+        assert lib.nufft_plan(C.byref(d), None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+
+
+def test_bad_weights_and_allocator_pairing():
+    lib = N.load()
+    xy = np.zeros((3, 2))
+    hw = np.array([1.0, -1.0, 1.0])
+    d = _desc(xy)
+    d.sensor_h = hw.ctypes.data_as(C.POINTER(C.c_double))
+    h = C.c_void_p()
+    assert lib.nufft_plan(C.byref(d), None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+    d = _desc(xy)
+    d.alloc = N.ALLOC_FN(lambda n, ctx: None)
+    assert lib.nufft_plan(C.byref(d), None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+
+
+def test_null_arguments():
+    lib = N.load()
+    assert lib.nufft_plan(None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.nufft_plan_destroy(None) == N.PAT_OK
+    sz = C.c_size_t()
+    assert lib.nufft_plan_workspace_size(None, C.byref(sz)) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_reconstruct(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_spectrum(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_forward(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_adjoint(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_timing_begin(None, 4) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_plan_desc_init(None) == N.PAT_ERR_INVALID_ARGUMENT
