@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--width-t", type=int, default=8)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-sample", type=int, default=8, help="lateral x-modes in the oracle sample")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="MiB of one plain device-to-device copy run before the timed loop (scales HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -156,6 +158,13 @@ def main():
     out = torch.empty(p.shape, dtype=plan.dtype, device=dev)
     log(f"plan info {plan.info}")
 
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        log(f"copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
+        del src, dst
     for _ in range(args.warmup):
         plan.reconstruct(g, out=out)
     torch.cuda.synchronize(dev)

@@ -33,27 +33,32 @@ inline int next_smooth_even(double v) {
   return (int)n;
 }
 
+// exact-division multiplier for x < 2^16, d < 2^16 (0 encodes d == 1)
+inline uint32_t div_magic(int d) { return d == 1 ? 0u : uint32_t((uint64_t(1) << 32) / uint64_t(d) + 1); }
+
 bool radix_plan(int n, patk::FftRaw& f) {
   f.n = n;
   f.npass = 0;
-  int r = n;
-  auto push = [&](int R) {
-    if (f.npass >= 16) return false;
-    f.radix[f.npass++] = R;
-    r /= R;
-    return true;
-  };
-  while (r % 8 == 0)
-    if (!push(8)) return false;
-  while (r % 4 == 0)
-    if (!push(4)) return false;
-  while (r % 2 == 0)
-    if (!push(2)) return false;
-  while (r % 5 == 0)
-    if (!push(5)) return false;
-  while (r % 3 == 0)
-    if (!push(3)) return false;
-  return r == 1;
+  int radix[24], np = 0, r = n;
+  for (int R : {8, 4, 2, 5, 3})
+    while (r % R == 0 && np < 24) {
+      radix[np++] = R;
+      r /= R;
+    }
+  if (r != 1 || np > 12 || n >= 65536) return false;
+  int p = 1;
+  for (int i = 0; i < np; ++i) {
+    patk::FftPassRaw& ps = f.pass[i];
+    ps.R = radix[i];
+    ps.p = p;
+    ps.nbf = n / radix[i];
+    ps.twstep = n / (p * radix[i]);
+    ps.m_nbf = div_magic(ps.nbf);
+    ps.m_p = div_magic(p);
+    p *= radix[i];
+  }
+  f.npass = np;
+  return true;
 }
 
 struct HostBlob {
@@ -165,10 +170,18 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.w_t = d.width_t;
   dp.kahan = d.precision == PAT_FP32_KAHAN;
   const size_t cxb = 2 * sizeof(T);
-  // FFT lengths the LDS kernels handle (one transform of n complex per work-group within 64 KiB)
-  if ((size_t)dp.n_t * cxb > 65536 || (size_t)(dp.n_x + 1) * cxb > 65536 || (size_t)(dp.n_y + 1) * cxb > 65536 ||
-      (size_t)(d.nx + 1) * cxb > 65536 || (size_t)(d.ny + 1) * cxb > 65536 || (size_t)(d.nz + 1) * cxb > 65536)
+  // FFT lengths the LDS kernels handle: one padded sequence per work-group must fit the device's LDS
+  int lds_limit = 65536;
+  if (hipDeviceGetAttribute(&lds_limit, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return PAT_ERR_HIP;
+  }
+  auto seq_bytes = [&](int n) { return size_t(n + (n >> 3) + 1) * cxb; };
+  if (seq_bytes(dp.n_t) > (size_t)lds_limit || seq_bytes(dp.n_x) > (size_t)lds_limit ||
+      seq_bytes(dp.n_y) > (size_t)lds_limit || seq_bytes(d.nx) > (size_t)lds_limit ||
+      seq_bytes(d.ny) > (size_t)lds_limit || seq_bytes(d.nz) > (size_t)lds_limit)
     return PAT_ERR_UNSUPPORTED;
+  if (dp.n_t > 8192) return PAT_ERR_UNSUPPORTED;  // temporal kernel: 512 threads x 16 values
   if (dp.n_x > 4096 || dp.n_y > 4096 || d.nx > 2048 || d.ny > 2048 || d.nz > 2048) return PAT_ERR_UNSUPPORTED;
   if (!radix_plan(dp.n_t, dp.f_nt) || !radix_plan(dp.n_x, dp.f_nx) || !radix_plan(dp.n_y, dp.f_ny) ||
       !radix_plan(d.nx, dp.f_Nx) || !radix_plan(d.ny, dp.f_Ny) || !radix_plan(d.nz, dp.f_Nz))
@@ -284,6 +297,9 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t o_tw_Nx = add_twiddles<T>(blob, d.nx);
   const size_t o_tw_Ny = add_twiddles<T>(blob, d.ny);
   const size_t o_tw_Nz = add_twiddles<T>(blob, d.nz);
+  patk::FftRaw* ffts[6] = {&dp.f_nt, &dp.f_nx, &dp.f_ny, &dp.f_Nx, &dp.f_Ny, &dp.f_Nz};
+  size_t o_pass[6];
+  for (int i = 0; i < 6; ++i) o_pass[i] = blob.add(ffts[i]->pass, sizeof(patk::FftPassRaw) * ffts[i]->npass);
 
   P->dev_bytes = align_up(blob.bytes.size());
   P->dev = dev_alloc(d, P->dev_bytes);
@@ -311,6 +327,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.f_Nx.tw = at(o_tw_Nx);
   dp.f_Ny.tw = at(o_tw_Ny);
   dp.f_Nz.tw = at(o_tw_Nz);
+  for (int i = 0; i < 6; ++i) ffts[i]->dpass = at(o_pass[i]);
 
   // workspace: region A = grid U (later the lateral spectra Gh);
   // region B = per-sensor bins Gt, then rows V, then the spectrum F.

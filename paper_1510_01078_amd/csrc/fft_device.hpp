@@ -2,14 +2,15 @@
 // mixed-radix FFT for gfx950 work-groups.
 //
 // A work-group transforms `batch` sequences of length n that live in LDS
-// (sequence f starts at buf + f*bstride). Each radix-R pass reads the R
-// inputs of every butterfly into registers, applies the twiddles and the
-// length-R DFT, waits at a barrier, then writes the outputs in Stockham
-// order, so the transform runs in place in one LDS buffer and leaves the
-// result in natural order. With p the product of the radices already done,
-// butterfly i (0 <= i < n/R, k = i mod p) reads x[i + r*n/R], multiplies
-// input r by w^(r*k*n/(p*R)) with w = exp(-2*pi*i/n) (conjugated for the
-// inverse) and writes output r to position (i-k)*R + k + r*p.
+// (sequence f starts at buf + f*bstride, element a at slot lpos(a)). Each
+// radix-R pass reads the R inputs of every butterfly into registers,
+// applies the twiddles and the length-R DFT, waits at a barrier, then
+// writes the outputs in Stockham order, so the transform runs in place in
+// one LDS buffer and leaves the result in natural order. With p the product
+// of the radices already done, butterfly i (0 <= i < n/R, k = i mod p)
+// reads x[i + r*n/R], multiplies input r by w^(r*k*n/(p*R)) with
+// w = exp(-2*pi*i/n) (conjugated for the inverse) and writes output r to
+// position (i-k)*R + k + r*p.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -36,15 +37,59 @@ __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return cx<T>{a.x * s, a.
 template <typename T>
 __device__ __forceinline__ cx<T> mul_is(cx<T> a, T s) { return cx<T>{-s * a.y, s * a.x}; }
 
-// Descriptor of one FFT length: the radix sequence and its twiddle table
+// One radix pass: radix R, p = product of the radices before it, nbf = n/R
+// butterflies per sequence, twstep = n/(p*R), and multipliers for exact
+// division by nbf and by p (q = umulhi(x, m) for x < 2^16; m = 0 marks a
+// divisor of 1).
+struct FftPass {
+  int R, p, nbf, twstep;
+  uint32_t m_nbf, m_p;
+};
+
+// Descriptor of one FFT length: the pass sequence and its twiddle table
 // tw[t] = exp(-2*pi*i*t/n), t = 0..n-1 (computed in double on the host).
 template <typename T>
 struct FftDesc {
   int n;
   int npass;
-  int radix[16];
+  const FftPass* pass;  // device array of npass entries
   const cx<T>* tw;
 };
+
+__device__ __forceinline__ int fdiv(int x, uint32_t m) { return m ? int(__umulhi(uint32_t(x), m)) : x; }
+
+// Exact x / d for 0 <= x, d < 2^16 by a multiply-high (the multiplier is
+// computed once, so loops over flattened indices avoid integer division).
+struct FastDiv {
+  uint32_t m;
+  __device__ __forceinline__ explicit FastDiv(int d) : m(d == 1 ? 0u : 0xFFFFFFFFu / uint32_t(d) + 1u) {}
+  __device__ __forceinline__ int operator()(int x) const { return m ? int(__umulhi(uint32_t(x), m)) : x; }
+};
+
+// Move `count` elements through registers: every thread first issues all of
+// its (at most U) loads, then all of its stores, so many global accesses are
+// in flight at once. Requires count <= U * nthr.
+template <int U, typename Load, typename Store>
+__device__ __forceinline__ void staged_copy(int count, int tid, int nthr, Load ld, Store st) {
+  using V = decltype(ld(0));
+  V tmp[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * nthr;
+    if (q < count) tmp[u] = ld(q);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int q = tid + u * nthr;
+    if (q < count) st(q, tmp[u]);
+  }
+}
+
+// LDS slot of element a of a sequence: one pad slot after every 8 elements,
+// so the stride-R stores of the first radix-8 passes hit distinct banks.
+__host__ __device__ __forceinline__ constexpr int lpos(int a) { return a + (a >> 3); }
+// Slots one sequence of length n occupies (odd, so sequences start on different banks).
+__host__ __device__ __forceinline__ constexpr int lseq(int n) { return n + (n >> 3) + 1; }
 
 // Length-R DFT in place; INV selects exp(+2 pi i rk/R).
 template <typename T, int R, bool INV>
@@ -133,29 +178,30 @@ struct Dft<T, 5, INV> {
 };
 
 // One radix-R Stockham pass over `batch` sequences; every thread holds at
-// most MAXV values, so batch*n <= MAXV*nthr is required.
+// most MAXV values, so batch*n <= MAXV*nthr is required (and batch*n < 2^16).
 template <typename T, int R, int MAXV, bool INV>
-__device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int p, int batch, int bstride,
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int batch, int bstride,
                                               const cx<T>* __restrict__ tw, int tid, int nthr) {
   constexpr int K = (MAXV + R - 1) / R;
-  const int nbf = n / R;
+  const int nbf = ps.nbf;
+  const int p = ps.p;
   const int total = nbf * batch;
-  const int twstep = n / (p * R);
   cx<T> v[K][R];
 #pragma unroll
   for (int it = 0; it < K; ++it) {
     const int idx = tid + it * nthr;
     if (idx < total) {
-      const int f = idx / nbf;
+      const int f = fdiv(idx, ps.m_nbf);
       const int i = idx - f * nbf;
       const cx<T>* src = buf + f * bstride;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[it][r] = src[i + r * nbf];
-      const int k = i % p;
+      for (int r = 0; r < R; ++r) v[it][r] = src[lpos(i + r * nbf)];
+      const int k = i - fdiv(i, ps.m_p) * p;
       if (k != 0) {
+        const int ts = k * ps.twstep;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[r * k * twstep];
+          cx<T> w = tw[r * ts];
           if (INV) w.y = -w.y;
           v[it][r] = cmul(v[it][r], w);
         }
@@ -168,13 +214,13 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int p, int batc
   for (int it = 0; it < K; ++it) {
     const int idx = tid + it * nthr;
     if (idx < total) {
-      const int f = idx / nbf;
+      const int f = fdiv(idx, ps.m_nbf);
       const int i = idx - f * nbf;
-      const int k = i % p;
+      const int k = i - fdiv(i, ps.m_p) * p;
       cx<T>* dst = buf + f * bstride;
-      const int j = (i - k) * R + k;
+      const int j0 = (i - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[j + r * p] = v[it][r];
+      for (int r = 0; r < R; ++r) dst[lpos(j0 + r * p)] = v[it][r];
     }
   }
   __syncthreads();
@@ -182,18 +228,16 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, int n, int p, int batc
 
 // Full transform (all passes). Callers must __syncthreads() after filling buf.
 template <typename T, int MAXV, bool INV>
-__device__ void fft_lds(cx<T>* buf, const FftDesc<T>& fd, int batch, int bstride, int tid, int nthr) {
-  int p = 1;
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int batch, int bstride, int tid, int nthr) {
   for (int s = 0; s < fd.npass; ++s) {
-    const int R = fd.radix[s];
-    switch (R) {
-      case 8: stockham_pass<T, 8, MAXV, INV>(buf, fd.n, p, batch, bstride, fd.tw, tid, nthr); break;
-      case 4: stockham_pass<T, 4, MAXV, INV>(buf, fd.n, p, batch, bstride, fd.tw, tid, nthr); break;
-      case 2: stockham_pass<T, 2, MAXV, INV>(buf, fd.n, p, batch, bstride, fd.tw, tid, nthr); break;
-      case 3: stockham_pass<T, 3, MAXV, INV>(buf, fd.n, p, batch, bstride, fd.tw, tid, nthr); break;
-      default: stockham_pass<T, 5, MAXV, INV>(buf, fd.n, p, batch, bstride, fd.tw, tid, nthr); break;
+    const FftPass ps = fd.pass[s];
+    switch (ps.R) {
+      case 8: stockham_pass<T, 8, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 4: stockham_pass<T, 4, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 2: stockham_pass<T, 2, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 3: stockham_pass<T, 3, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      default: stockham_pass<T, 5, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
     }
-    p *= R;
   }
 }
 

@@ -30,23 +30,30 @@ struct MaxV<double> {
 };
 
 // Sequences of length n one FFT work-group holds: limited by the register
-// staging (MaxV values per thread) and by 64 KiB of LDS with one pad element
-// per sequence.
+// staging (MaxV values per thread) and by a 64 KiB LDS budget for the padded
+// sequences (a single sequence may exceed it; the plan checks the device limit).
 template <typename T>
 static int lds_batch(int n, int cap) {
   int b = MaxV<T>::v * 256 / n;
-  const int by_lds = int(65536 / (size_t(n + 1) * 2 * sizeof(T)));
+  const int by_lds = int(65536 / (size_t(lseq(n)) * 2 * sizeof(T)));
   if (b > by_lds) b = by_lds;
   if (b > cap) b = cap;
-  return b;
+  return b < 1 ? 1 : b;
+}
+
+// Allow a kernel more than the default dynamic LDS when a launch needs it.
+static hipError_t allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 template <typename T>
 static FftDesc<T> as_desc(const FftRaw& r) {
   FftDesc<T> d;
+  static_assert(sizeof(FftPass) == sizeof(FftPassRaw), "pass layout");
   d.n = r.n;
   d.npass = r.npass;
-  for (int i = 0; i < 16; ++i) d.radix[i] = r.radix[i];
+  d.pass = static_cast<const FftPass*>(r.dpass);
   d.tw = static_cast<const cx<T>*>(r.tw);
   return d;
 }
@@ -77,28 +84,31 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
   const int m0 = 2 * blockIdx.x;
   const int m1 = m0 + 1;
   const bool has1 = m1 < M;
-  for (int q = tid; q < n_t; q += nthr) buf[q] = cx<T>{T(0), T(0)};
+  for (int q = tid; q < lseq(n_t); q += nthr) buf[q] = cx<T>{T(0), T(0)};
   __syncthreads();
   const T w0 = hw[m0];
   const T w1 = has1 ? hw[m1] : T(0);
   const T* g0 = g + size_t(m0) * Nt;
   const T* g1 = g + size_t(has1 ? m1 : m0) * Nt;
-  for (int n = tid; n < Nt; n += nthr) {
-    const T d = deap[n];
-    const T a = g0[n] * w0 * d;
-    const T b = has1 ? g1[n] * w1 * d : T(0);
-    int pos = n - n0;
-    if (pos < 0) pos += n_t;
-    buf[pos] = cx<T>{a, b};
-  }
+  staged_copy<kTemporalMaxV>(
+      Nt, tid, nthr,
+      [&](int n) {
+        const T d = deap[n];
+        return cx<T>{g0[n] * w0 * d, has1 ? g1[n] * w1 * d : T(0)};
+      },
+      [&](int n, cx<T> v) {
+        int pos = n - n0;
+        if (pos < 0) pos += n_t;
+        buf[lpos(pos)] = v;
+      });
   __syncthreads();
-  fft_lds<T, kTemporalMaxV, false>(buf, fd, 1, n_t, tid, nthr);
+  fft_lds<T, kTemporalMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
   cx<T>* o0 = Gt + size_t(m0) * nb;
   cx<T>* o1 = Gt + size_t(m1) * nb;
   for (int i = tid; i < nb; i += nthr) {
     const int b = b_lo + i;
-    const cx<T> z = buf[imod(b, n_t)];
-    const cx<T> zm = buf[imod(-b, n_t)];
+    const cx<T> z = buf[lpos(imod(b, n_t))];
+    const cx<T> zm = buf[lpos(imod(-b, n_t))];
     // transform of the real part: (Z_b + conj Z_-b)/2; of the imaginary part: (Z_b - conj Z_-b)/(2i)
     o0[i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
     if (has1) o1[i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
@@ -108,7 +118,9 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
 template <typename T>
 hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s) {
   const int blocks = (p.M + 1) / 2;
-  const size_t lds = size_t(p.n_t) * sizeof(cx<T>);
+  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T>), lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
                      static_cast<const T*>(p.hw), static_cast<const T*>(p.deap), as_desc<T>(p.f_nt), p.b_lo, p.nb,
                      static_cast<cx<T>*>(Gt));
@@ -116,15 +128,36 @@ hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// Stage 1: lateral spreading (the gridding of eq. NED_NUFFT), one temporal
-// bin chunk at a time. Output-driven and atomic-free: a work-group owns a
-// 16x16 tile of the oversampled grid (four waves, each a 16x4 patch), and
+// Stage 1: lateral spreading (the gridding of eq. NED_NUFFT), one chunk of
+// temporal bins at a time. Output-driven and atomic-free: a work-group owns a
+// 16x16 tile of the oversampled grid (four waves, each a 16x4 patch) and
 // every lane owns one grid point, accumulating in registers the
 // contributions of the tile's sensor list in list order (deterministic).
-// The sensor's bin values are wave-uniform (scalar loads); its weight at the
-// lane's point is wx[tx]*wy[ty] (0 outside the footprint).
+// The list is staged through LDS in batches (sensor footprint origin,
+// per-axis weights, the chunk's bin values), so the inner loop reads only
+// LDS: the bin values are wave-uniform broadcasts and the lane's weight is
+// wx[tx]*wy[ty] (0 outside the footprint).
 // ---------------------------------------------------------------------------
 constexpr int kSpreadBins = 16;
+constexpr int kSpreadBatch = 64;
+constexpr int kMaxW = 16;
+
+template <typename T, bool KAHAN>
+__device__ __forceinline__ void accum(cx<T>& a, cx<T>& c, T wt, cx<T> g) {
+  if (KAHAN) {
+    const T yr = wt * g.x - c.x;
+    const T tr = a.x + yr;
+    c.x = (tr - a.x) - yr;
+    a.x = tr;
+    const T yi = wt * g.y - c.y;
+    const T ti = a.y + yi;
+    c.y = (ti - a.y) - yi;
+    a.y = ti;
+  } else {
+    a.x += wt * g.x;
+    a.y += wt * g.y;
+  }
+}
 
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
@@ -133,12 +166,17 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
                                                 const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
                                                 int nchunks, cx<T>* __restrict__ U) {
   constexpr int BC = kSpreadBins;
+  constexpr int SB = kSpreadBatch;
+  __shared__ int s_bx[SB], s_by[SB];
+  __shared__ T s_wx[SB * kMaxW], s_wy[SB * kMaxW];
+  __shared__ cx<T> s_g[SB * BC];
   const int chunk = blockIdx.x % nchunks;
   const int tile = blockIdx.x / nchunks;
   const int tyi = tile / tiles_x;
   const int txi = tile - tyi * tiles_x;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int px = txi * kSpreadTile + (lane & 15);
   const int prow0 = tyi * kSpreadTile + wave * 4;
   const int py = prow0 + (lane >> 4);
@@ -148,64 +186,45 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   cx<T> cmp[KAHAN ? BC : 1];
 #pragma unroll
   for (int b = 0; b < BC; ++b) acc[b] = cx<T>{T(0), T(0)};
-  if (KAHAN) {
 #pragma unroll
-    for (int b = 0; b < (KAHAN ? BC : 1); ++b) cmp[b] = cx<T>{T(0), T(0)};
-  }
+  for (int b = 0; b < (KAHAN ? BC : 1); ++b) cmp[b] = cx<T>{T(0), T(0)};
   const int q_begin = tile_off[tile];
   const int q_end = tile_off[tile + 1];
-  for (int q = q_begin; q < q_end; ++q) {
-    const int sidx = tile_sens[q];
-    const int by = sby[sidx];
-    int d0 = prow0 - by;
-    if (d0 < 0) d0 += n_y;
-    if (!(d0 < w || d0 + 3 >= n_y)) continue;  // footprint misses this wave's four rows
-    const int bx = sbx[sidx];
-    int tx = px - bx;
-    if (tx < 0) tx += n_x;
-    int ty = py - by;
-    if (ty < 0) ty += n_y;
-    T wt = T(0);
-    if (tx < w && ty < w) wt = swx[sidx * w + tx] * swy[sidx * w + ty];
-    const cx<T>* gs = Gt + size_t(sidx) * nb + b0;
-    if (nbc == BC) {
-#pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        const cx<T> gv = gs[b];
-        if (KAHAN) {
-          T yr = wt * gv.x - cmp[b].x;
-          T tr = acc[b].x + yr;
-          cmp[b].x = (tr - acc[b].x) - yr;
-          acc[b].x = tr;
-          T yi = wt * gv.y - cmp[b].y;
-          T ti = acc[b].y + yi;
-          cmp[b].y = (ti - acc[b].y) - yi;
-          acc[b].y = ti;
-        } else {
-          acc[b].x += wt * gv.x;
-          acc[b].y += wt * gv.y;
-        }
+  for (int qb = q_begin; qb < q_end; qb += SB) {
+    const int nq = min(SB, q_end - qb);
+    __syncthreads();  // the previous batch has been consumed
+    for (int t = tid; t < nq; t += 256) {
+      const int sidx = tile_sens[qb + t];
+      s_bx[t] = sbx[sidx];
+      s_by[t] = sby[sidx];
+    }
+    for (int t = tid; t < nq * kMaxW; t += 256) {
+      const int qi = t >> 4, ti = t & (kMaxW - 1);
+      if (ti < w) {
+        const int sidx = tile_sens[qb + qi];
+        s_wx[t] = swx[sidx * w + ti];
+        s_wy[t] = swy[sidx * w + ti];
       }
-    } else {
+    }
+    for (int t = tid; t < nq * BC; t += 256) {
+      const int qi = t / BC, bi = t - qi * BC;
+      const int sidx = tile_sens[qb + qi];
+      s_g[t] = bi < nbc ? Gt[size_t(sidx) * nb + b0 + bi] : cx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+    for (int qi = 0; qi < nq; ++qi) {
+      const int by = s_by[qi];
+      int d0 = prow0 - by;
+      if (d0 < 0) d0 += n_y;
+      if (!(d0 < w || d0 + 3 >= n_y)) continue;  // footprint misses this wave's four rows
+      int tx = px - s_bx[qi];
+      if (tx < 0) tx += n_x;
+      int ty = py - by;
+      if (ty < 0) ty += n_y;
+      const T wt = (tx < w && ty < w) ? s_wx[qi * kMaxW + tx] * s_wy[qi * kMaxW + ty] : T(0);
+      const cx<T>* gq = s_g + qi * BC;
 #pragma unroll
-      for (int b = 0; b < BC; ++b) {
-        if (b < nbc) {
-          const cx<T> gv = gs[b];
-          if (KAHAN) {
-            T yr = wt * gv.x - cmp[b].x;
-            T tr = acc[b].x + yr;
-            cmp[b].x = (tr - acc[b].x) - yr;
-            acc[b].x = tr;
-            T yi = wt * gv.y - cmp[b].y;
-            T ti = acc[b].y + yi;
-            cmp[b].y = (ti - acc[b].y) - yi;
-            acc[b].y = ti;
-          } else {
-            acc[b].x += wt * gv.x;
-            acc[b].y += wt * gv.y;
-          }
-        }
-      }
+      for (int b = 0; b < BC; ++b) accum<T, KAHAN>(acc[b], cmp[KAHAN ? b : 0], wt, gq[b]);
     }
   }
   if (px < n_x && py < n_y) {
@@ -219,6 +238,7 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
 
 template <typename T>
 hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t s) {
+  if (p.w_xy > kMaxW) return hipErrorInvalidValue;
   const int nchunks = (p.nb + kSpreadBins - 1) / kSpreadBins;
   const long long blocks = (long long)p.tiles_x * p.tiles_y * nchunks;
   if (p.kahan)
@@ -247,32 +267,41 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_x = fd.n;
-  const int bstride = n_x + 1;
+  const int bstride = lseq(n_x);
   const int b = blockIdx.y;
   const int py0 = blockIdx.x * rows;
   const int nr = min(rows, n_y - py0);
   const cx<T>* src = U + (size_t(b) * n_y + py0) * n_x;
-  for (int q = tid; q < nr * n_x; q += nthr) {
-    const int r = q / n_x;
-    const int px = q - r * n_x;
-    buf[r * bstride + px] = src[q];
-  }
+  const FastDiv div_nx(n_x), div_nr(nr);
+  staged_copy<MaxV<T>::v>(
+      nr * n_x, tid, nthr, [&](int q) { return src[q]; },
+      [&](int q, cx<T> v) {
+        const int r = div_nx(q);
+        buf[r * bstride + lpos(q - r * n_x)] = v;
+      });
   __syncthreads();
   fft_lds<T, MaxV<T>::v, false>(buf, fd, nr, bstride, tid, nthr);
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
-  for (int q = tid; q < nr * Nx; q += nthr) {
-    const int jj = q / nr;
-    const int r = q - jj * nr;
-    const int j = jj < Nx / 2 ? jj : jj - Nx;
-    dst[size_t(jj) * n_y + r] = buf[r * bstride + (j < 0 ? j + n_x : j)];
-  }
+  staged_copy<MaxV<T>::v>(
+      nr * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nr(q);
+        const int r = q - jj * nr;
+        const int j = jj < Nx / 2 ? jj : jj - Nx;
+        return buf[r * bstride + lpos(j < 0 ? j + n_x : j)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nr(q);
+        dst[size_t(jj) * n_y + (q - jj * nr)] = v;
+      });
 }
 
 template <typename T>
 hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, hipStream_t s) {
   const int rows = lds_batch<T>(p.n_x, 16);
-  if (rows < 1) return hipErrorInvalidValue;
-  const size_t lds = size_t(rows) * (p.n_x + 1) * sizeof(cx<T>);
+  const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x<T>), lds);
+  if (e != hipSuccess) return e;
   dim3 grid((p.n_y + rows - 1) / rows, p.nb);
   hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
                      as_desc<T>(p.f_nx), static_cast<cx<T>*>(V));
@@ -292,34 +321,47 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_y = fd.n;
-  const int bstride = n_y + 1;
+  const int bstride = lseq(n_y);
   const int jj = blockIdx.y;
   const int b0 = blockIdx.x * bins;
   const int nbc = min(bins, nb - b0);
-  for (int q = tid; q < nbc * n_y; q += nthr) {
-    const int bi = q / n_y;
-    const int py = q - bi * n_y;
-    buf[bi * bstride + py] = V[(size_t(b0 + bi) * Nx + jj) * n_y + py];
-  }
+  const FastDiv div_ny(n_y), div_nbc(nbc);
+  staged_copy<MaxV<T>::v>(
+      nbc * n_y, tid, nthr,
+      [&](int q) {
+        const int bi = div_ny(q);
+        return V[(size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y)];
+      },
+      [&](int q, cx<T> v) {
+        const int bi = div_ny(q);
+        buf[bi * bstride + lpos(q - bi * n_y)] = v;
+      });
   __syncthreads();
   fft_lds<T, MaxV<T>::v, false>(buf, fd, nbc, bstride, tid, nthr);
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
-  for (int q = tid; q < nbc * Ny; q += nthr) {
-    const int kk = q / nbc;
-    const int bi = q - kk * nbc;
-    const int k = kk < Ny / 2 ? kk : kk - Ny;
-    const T sc = cxj * dcy[kk];
-    const cx<T> v = buf[bi * bstride + (k < 0 ? k + n_y : k)];
-    dst[size_t(kk) * nb + bi] = cx<T>{v.x * sc, v.y * sc};
-  }
+  staged_copy<MaxV<T>::v>(
+      nbc * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nbc(q);
+        const int bi = q - kk * nbc;
+        const int k = kk < Ny / 2 ? kk : kk - Ny;
+        const T sc = cxj * dcy[kk];
+        const cx<T> v = buf[bi * bstride + lpos(k < 0 ? k + n_y : k)];
+        return cx<T>{v.x * sc, v.y * sc};
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nbc(q);
+        dst[size_t(kk) * nb + (q - kk * nbc)] = v;
+      });
 }
 
 template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
   const int bins = lds_batch<T>(p.n_y, 16);
-  if (bins < 1) return hipErrorInvalidValue;
-  const size_t lds = size_t(bins) * (p.n_y + 1) * sizeof(cx<T>);
+  const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y<T>), lds);
+  if (e != hipSuccess) return e;
   dim3 grid((p.nb + bins - 1) / bins, p.Nx);
   hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
                      bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
@@ -406,22 +448,33 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Nx = fd.n;
-  const int bstride = Nx + 1;
+  const int bstride = lseq(Nx);
   const int kk = blockIdx.y;
   const int l0 = blockIdx.x * lchunk;
   const int nl = min(lchunk, Lh - l0);
-  for (int q = tid; q < nl * Nx; q += nthr) {
-    const int jj = q / nl;
-    const int li = q - jj * nl;
-    buf[li * bstride + jj] = F[(size_t(jj) * Ny + kk) * Lh + l0 + li];
-  }
+  const FastDiv div_nl(nl);
+  staged_copy<MaxV<T>::v>(
+      nl * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nl(q);
+        return F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nl(q);
+        buf[(q - jj * nl) * bstride + lpos(jj)] = v;
+      });
   __syncthreads();
   fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
-  for (int q = tid; q < nl * Nx; q += nthr) {
-    const int jj = q / nl;
-    const int li = q - jj * nl;
-    F[(size_t(jj) * Ny + kk) * Lh + l0 + li] = buf[li * bstride + jj];
-  }
+  staged_copy<MaxV<T>::v>(
+      nl * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nl(q);
+        return buf[(q - jj * nl) * bstride + lpos(jj)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nl(q);
+        F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)] = v;
+      });
 }
 
 template <typename T>
@@ -430,23 +483,34 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Ny = fd.n;
-  const int bstride = Ny + 1;
+  const int bstride = lseq(Ny);
   const int jj = blockIdx.y;
   const int l0 = blockIdx.x * lchunk;
   const int nl = min(lchunk, Lh - l0);
   cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
-  for (int q = tid; q < nl * Ny; q += nthr) {
-    const int kk = q / nl;
-    const int li = q - kk * nl;
-    buf[li * bstride + kk] = base[size_t(kk) * Lh + li];
-  }
+  const FastDiv div_nl(nl);
+  staged_copy<MaxV<T>::v>(
+      nl * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nl(q);
+        return base[size_t(kk) * Lh + (q - kk * nl)];
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nl(q);
+        buf[(q - kk * nl) * bstride + lpos(kk)] = v;
+      });
   __syncthreads();
   fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
-  for (int q = tid; q < nl * Ny; q += nthr) {
-    const int kk = q / nl;
-    const int li = q - kk * nl;
-    base[size_t(kk) * Lh + li] = buf[li * bstride + kk];
-  }
+  staged_copy<MaxV<T>::v>(
+      nl * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nl(q);
+        return buf[(q - kk * nl) * bstride + lpos(kk)];
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nl(q);
+        base[size_t(kk) * Lh + (q - kk * nl)] = v;
+      });
 }
 
 template <typename T>
@@ -457,23 +521,27 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Nz = fd.n;
   const int Lh = Nz / 2 + 1;
-  const int bstride = Nz + 1;
+  const int bstride = lseq(Nz);
   const long long r0 = (long long)blockIdx.x * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
-  for (int q = tid; q < nr * Lh; q += nthr) {
-    const int r = q / Lh;
-    const int l = q - r * Lh;
-    const cx<T> v = F[(r0 + r) * Lh + l];
-    buf[r * bstride + l] = v;
-    if (l > 0 && l < Nz / 2) buf[r * bstride + Nz - l] = cx<T>{v.x, -v.y};
-  }
+  const FastDiv div_lh(Lh), div_nz(Nz);
+  staged_copy<MaxV<T>::v>(
+      nr * Lh, tid, nthr, [&](int q) { return F[r0 * Lh + q]; },
+      [&](int q, cx<T> v) {
+        const int r = div_lh(q);
+        const int l = q - r * Lh;
+        buf[r * bstride + lpos(l)] = v;
+        if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
+      });
   __syncthreads();
   fft_lds<T, MaxV<T>::v, true>(buf, fd, nr, bstride, tid, nthr);
-  for (int q = tid; q < nr * Nz; q += nthr) {
-    const int r = q / Nz;
-    const int e = q - r * Nz;
-    f[(r0 + r) * Nz + e] = buf[r * bstride + e].x;
-  }
+  staged_copy<MaxV<T>::v>(
+      nr * Nz, tid, nthr,
+      [&](int q) {
+        const int r = div_nz(q);
+        return buf[r * bstride + lpos(q - r * Nz)].x;
+      },
+      [&](int q, T v) { f[r0 * Nz + q] = v; });
 }
 
 template <typename T>
@@ -482,28 +550,32 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   const int Lh = p.Nz / 2 + 1;
   {
     const int lc = lds_batch<T>(p.Nx, 16);
-    if (lc < 1) return hipErrorInvalidValue;
+    const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_x<T>), lds);
+    if (e != hipSuccess) return e;
     dim3 grid((Lh + lc - 1) / lc, p.Ny);
-    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(kFftThreads), size_t(lc) * (p.Nx + 1) * sizeof(cx<T>), s, F, p.Ny, Lh,
-                       lc, as_desc<T>(p.f_Nx));
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(kFftThreads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx));
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
     const int lc = lds_batch<T>(p.Ny, 16);
-    if (lc < 1) return hipErrorInvalidValue;
+    const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_y<T>), lds);
+    if (e != hipSuccess) return e;
     dim3 grid((Lh + lc - 1) / lc, p.Nx);
-    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(kFftThreads), size_t(lc) * (p.Ny + 1) * sizeof(cx<T>), s, F, Lh, lc,
-                       as_desc<T>(p.f_Ny));
-    hipError_t e = hipGetLastError();
+    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(kFftThreads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny));
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
     const int rows = lds_batch<T>(p.Nz, 16);
-    if (rows < 1) return hipErrorInvalidValue;
+    const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds);
+    if (e != hipSuccess) return e;
     const long long nrows = (long long)p.Nx * p.Ny;
-    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(kFftThreads),
-                       size_t(rows) * (p.Nz + 1) * sizeof(cx<T>), s, F, nrows, rows, as_desc<T>(p.f_Nz), f);
+    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(kFftThreads), lds, s, F, nrows,
+                       rows, as_desc<T>(p.f_Nz), f);
   }
   return hipGetLastError();
 }

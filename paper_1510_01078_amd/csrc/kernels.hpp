@@ -6,11 +6,17 @@
 
 namespace patk {
 
+struct FftPassRaw {
+  int R = 0, p = 0, nbf = 0, twstep = 0;
+  uint32_t m_nbf = 0, m_p = 0;
+};
+
 struct FftRaw {
   int n = 0;
   int npass = 0;
-  int radix[16] = {0};
-  const void* tw = nullptr;  // device, n complex entries exp(-2 pi i t/n)
+  FftPassRaw pass[12];           // host copy
+  const void* dpass = nullptr;   // device copy of pass[0..npass)
+  const void* tw = nullptr;      // device, n complex entries exp(-2 pi i t/n)
 };
 
 // Everything a launch needs, as plain values and device pointers.
