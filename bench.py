@@ -188,11 +188,14 @@ def main():
     names = ["temporal_fft", "spread", "lateral_fft_x", "lateral_fft_y_deconv", "gather_weight", "inverse_fft"]
     stages = {n: {"ms": round(a, 5), "bytes": int(b), "GB_s": round(b / (a * 1e-3) / 1e9, 1) if a > 0 else None}
               for n, a, b in zip(names, avg_ms, sb)}
-    spread_ms = avg_ms[1]
-    achieved = sb[1] / (spread_ms * 1e-3) / 1e9
+    rounds = max(1, plan.info["rounds"])
+    spread_ms = avg_ms[1] / rounds
+    spread_bytes_launch = sb[1] / rounds
+    achieved = spread_bytes_launch / (spread_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spread",
-                "bytes_per_launch": int(sb[1]), "ms_per_launch": round(spread_ms, 5)}
+                "bytes_per_launch": int(spread_bytes_launch), "ms_per_launch": round(spread_ms, 5),
+                "launches_per_step": rounds}
 
     result = {
         "metric": METRIC,

@@ -118,6 +118,8 @@ typedef struct pat_plan_info {
   int64_t spread_pairs;      /* (sensor, tile) incidences in the spread lists */
   size_t workspace_bytes;
   size_t table_bytes;        /* device bytes owned by the plan */
+  int32_t chunk_bins;        /* temporal bins per spread / x-FFT round */
+  int32_t rounds;            /* spread / x-FFT rounds per call */
 } pat_plan_info;
 
 /* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, NULL
@@ -168,9 +170,10 @@ pat_status pat_adjoint(pat_plan* plan, const void* g, void* f, void* workspace, 
  * calls (allocation happens here, not in the compute calls). pat_timing_end
  * synchronises on the last event, writes the summed milliseconds of each
  * stage to ms[0..nstage-1] (nstage <= PAT_TIMING_STAGES), the number of
- * recorded calls to *calls, and destroys the events. Stages:
- * 0 temporal FFT, 1 lateral spread, 2 lateral FFT along x, 3 lateral FFT
- * along y with deconvolution, 4 temporal gather and weight, 5 inverse FFT. */
+ * recorded calls to *calls, and destroys the events. Stages: 0 temporal FFT,
+ * 1 lateral spread, 2 lateral FFT along x, 3 lateral FFT along y with
+ * deconvolution, 4 temporal interpolation and weight, 5 inverse FFT (the
+ * spread and x-FFT run in rounds over bins; their rounds are summed). */
 #define PAT_TIMING_STAGES 6
 pat_status pat_timing_begin(pat_plan* plan, int32_t max_calls);
 pat_status pat_timing_end(pat_plan* plan, double* ms, int32_t nstage, int32_t* calls);

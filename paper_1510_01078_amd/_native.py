@@ -65,6 +65,8 @@ class PlanInfo(C.Structure):
         ("spread_pairs", C.c_int64),
         ("workspace_bytes", C.c_size_t),
         ("table_bytes", C.c_size_t),
+        ("chunk_bins", C.c_int32),
+        ("rounds", C.c_int32),
     ]
 
 

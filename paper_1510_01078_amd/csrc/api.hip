@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -97,10 +98,15 @@ struct pat_plan {
   patk::DevPlan dp;
   void* dev = nullptr;
   size_t dev_bytes = 0;
-  size_t off_B = 0;     // workspace: region A at 0 (grid / lateral spectra), region B at off_B
+  size_t off_B = 0;     // workspace regions: A at 0 (grid chunk / lateral spectra),
+  size_t off_C = 0;     // B at off_B (x rows / spectrum), C at off_C (per-sensor bins)
   size_t ws_bytes = 0;
   int64_t spread_pairs = 0;
-  std::vector<hipEvent_t> ev;  // PAT_TIMING_STAGES+1 per recorded call
+  // timing: per recorded call, marks_per_call events; mark i > 0 closes the
+  // interval of stage ev_stage[i] that began at mark i-1
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_stage;
+  int marks_per_call = 0;
   int ev_max = 0;
   int ev_used = 0;
 };
@@ -329,18 +335,31 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.f_Nz.tw = at(o_tw_Nz);
   for (int i = 0; i < 6; ++i) ffts[i]->dpass = at(o_pass[i]);
 
-  // workspace: region A = grid U (later the lateral spectra Gh);
-  // region B = per-sensor bins Gt, then rows V, then the spectrum F.
+  // Spread and x-FFT can run in rounds of chunk_bins bins through one smaller
+  // grid buffer (a multiple of the spread's 16-bin groups). One round is the
+  // default: on MI355X, rounds sized for the last-level cache measured slower
+  // (each round adds the spread's load-imbalance tail). PATNUFFT_CHUNK_BINS
+  // sets a round size (0 or >= nb: one round) to trade speed for workspace.
+  {
+    long cb = 0;
+    if (const char* env = std::getenv("PATNUFFT_CHUNK_BINS")) cb = std::atol(env);
+    if (cb <= 0 || cb >= dp.nb) cb = dp.nb;
+    cb = std::max<long>(16, (cb + 15) / 16 * 16);
+    dp.chunk_bins = int(std::min<long>(cb, dp.nb));
+  }
+  // workspace: region A = grid chunk U, later the lateral spectra Gh;
+  // region B = x-transformed rows V, later the spectrum F; region C = Gt.
   const size_t c = cxb;
   const size_t sz_Gt = size_t(M) * dp.nb * c;
-  const size_t sz_U = size_t(dp.nb) * dp.n_y * dp.n_x * c;
+  const size_t sz_U = size_t(dp.chunk_bins) * dp.n_y * dp.n_x * c;
   const size_t sz_V = size_t(dp.nb) * d.nx * dp.n_y * c;
   const size_t sz_Gh = size_t(d.nx) * d.ny * dp.nb * c;
   const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
   const size_t szA = align_up(std::max(sz_U, sz_Gh));
-  const size_t szB = align_up(std::max(sz_Gt, std::max(sz_V, sz_F)));
+  const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;
-  P->ws_bytes = szA + szB;
+  P->off_C = szA + szB;
+  P->ws_bytes = szA + szB + align_up(sz_Gt);
   return PAT_OK;
 }
 
@@ -363,37 +382,52 @@ struct DeviceGuard {
   }
 };
 
-inline void mark(pat_plan* P, int call, int stage, hipStream_t s) {
-  if (call >= 0) (void)hipEventRecord(P->ev[size_t(call) * (PAT_TIMING_STAGES + 1) + stage], s);
-}
+struct Marker {
+  pat_plan* P;
+  int call;
+  int next = 0;
+  hipStream_t s;
+  // record the next event of this call; `stage` names the work since the previous one
+  void operator()(int stage) {
+    if (call < 0 || next >= P->marks_per_call) return;
+    const size_t i = size_t(call) * P->marks_per_call + next;
+    P->ev_stage[i] = stage;
+    (void)hipEventRecord(P->ev[i], s);
+    ++next;
+  }
+};
+
+inline int rounds(const patk::DevPlan& dp) { return (dp.nb + dp.chunk_bins - 1) / dp.chunk_bins; }
 
 template <typename T>
 pat_status run(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, bool spectrum_only) {
   const patk::DevPlan& dp = P->dp;
   unsigned char* A = static_cast<unsigned char*>(ws);
   unsigned char* B = A + P->off_B;
-  int call = -1;
-  if (P->ev_used < P->ev_max) call = P->ev_used++;
+  unsigned char* C = A + P->off_C;
+  Marker mark{P, P->ev_used < P->ev_max ? P->ev_used++ : -1, 0, s};
   hipError_t e;
-  mark(P, call, 0, s);
-  if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), B, s)) != hipSuccess) return to_status(e);
-  mark(P, call, 1, s);
-  if ((e = patk::launch_spread<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
-  mark(P, call, 2, s);
-  if ((e = patk::launch_fft_x<T>(dp, A, B, s)) != hipSuccess) return to_status(e);
-  mark(P, call, 3, s);
+  mark(-1);
+  if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), C, s)) != hipSuccess) return to_status(e);
+  mark(0);
+  for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
+    const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
+    if ((e = patk::launch_spread<T>(dp, C, A, b0, b1, s)) != hipSuccess) return to_status(e);
+    mark(1);
+    if ((e = patk::launch_fft_x<T>(dp, A, B, b0, b1, s)) != hipSuccess) return to_status(e);
+    mark(2);
+  }
   if ((e = patk::launch_fft_y<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
-  mark(P, call, 4, s);
+  mark(3);
   if (spectrum_only) {
     if ((e = patk::launch_gather<T>(dp, A, out, true, s)) != hipSuccess) return to_status(e);
-    mark(P, call, 5, s);
-    mark(P, call, 6, s);
+    mark(4);
     return PAT_OK;
   }
   if ((e = patk::launch_gather<T>(dp, A, B, false, s)) != hipSuccess) return to_status(e);
-  mark(P, call, 5, s);
+  mark(4);
   if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s)) != hipSuccess) return to_status(e);
-  mark(P, call, 6, s);
+  mark(5);
   return PAT_OK;
 }
 
@@ -422,6 +456,7 @@ pat_status compute(pat_plan* P, const void* g, void* out, void* ws, void* stream
 void destroy_events(pat_plan* P) {
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
   P->ev.clear();
+  P->ev_stage.clear();
   P->ev_max = 0;
   P->ev_used = 0;
 }
@@ -489,6 +524,8 @@ pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
   info->spread_pairs = P->spread_pairs;
   info->workspace_bytes = P->ws_bytes;
   info->table_bytes = P->dev_bytes;
+  info->chunk_bins = P->dp.chunk_bins;
+  info->rounds = rounds(P->dp);
   return PAT_OK;
 }
 
@@ -530,8 +567,10 @@ pat_status pat_timing_begin(pat_plan* P, int32_t max_calls) {
   if (!P || max_calls < 1 || max_calls > 100000) return PAT_ERR_INVALID_ARGUMENT;
   DeviceGuard guard(P->device);
   destroy_events(P);
-  const size_t n = size_t(max_calls) * (PAT_TIMING_STAGES + 1);
+  P->marks_per_call = 5 + 2 * rounds(P->dp);
+  const size_t n = size_t(max_calls) * P->marks_per_call;
   P->ev.resize(n);
+  P->ev_stage.assign(n, -1);
   for (size_t i = 0; i < n; ++i) {
     if (hipEventCreate(&P->ev[i]) != hipSuccess) {
       P->ev.resize(i);
@@ -549,19 +588,19 @@ pat_status pat_timing_end(pat_plan* P, double* ms, int32_t nstage, int32_t* call
   DeviceGuard guard(P->device);
   for (int i = 0; i < nstage; ++i) ms[i] = 0.0;
   pat_status st = PAT_OK;
-  if (P->ev_used > 0) {
-    const size_t last = size_t(P->ev_used) * (PAT_TIMING_STAGES + 1) - 1;
-    if (hipEventSynchronize(P->ev[last]) != hipSuccess) st = PAT_ERR_HIP;
-    for (int c = 0; c < P->ev_used && st == PAT_OK; ++c)
-      for (int k = 0; k < nstage; ++k) {
-        float t = 0.f;
-        if (hipEventElapsedTime(&t, P->ev[size_t(c) * (PAT_TIMING_STAGES + 1) + k],
-                                P->ev[size_t(c) * (PAT_TIMING_STAGES + 1) + k + 1]) != hipSuccess) {
-          st = PAT_ERR_HIP;
-          break;
-        }
-        ms[k] += t;
+  if (P->ev_used > 0 && hipDeviceSynchronize() != hipSuccess) st = PAT_ERR_HIP;
+  for (int c = 0; c < P->ev_used && st == PAT_OK; ++c) {
+    const size_t base = size_t(c) * P->marks_per_call;
+    for (int k = 1; k < P->marks_per_call; ++k) {
+      const int stage = P->ev_stage[base + k];
+      if (stage < 0) break;
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, P->ev[base + k - 1], P->ev[base + k]) != hipSuccess) {
+        st = PAT_ERR_HIP;
+        break;
       }
+      if (stage < nstage) ms[stage] += t;
+    }
   }
   if (calls) *calls = P->ev_used;
   destroy_events(P);

@@ -18,24 +18,15 @@
 
 namespace patk {
 
-template <typename T>
-struct MaxV;
-template <>
-struct MaxV<float> {
-  static constexpr int v = 32;
-};
-template <>
-struct MaxV<double> {
-  static constexpr int v = 16;
-};
+constexpr int kFftMaxV = 16;  // values per thread in the FFT kernels
 
-// Sequences of length n one FFT work-group holds: limited by the register
-// staging (MaxV values per thread) and by a 64 KiB LDS budget for the padded
-// sequences (a single sequence may exceed it; the plan checks the device limit).
+// Sequences of length n per FFT work-group of nthr threads: at most kFftMaxV
+// values per thread, at most `cap`, and (when possible) within 80 KiB of LDS
+// so two work-groups share a CU.
 template <typename T>
-static int lds_batch(int n, int cap) {
-  int b = MaxV<T>::v * 256 / n;
-  const int by_lds = int(65536 / (size_t(lseq(n)) * 2 * sizeof(T)));
+static int fft_batch(int n, int nthr, int cap) {
+  int b = kFftMaxV * nthr / n;
+  const int by_lds = int(81920 / (size_t(lseq(n)) * 2 * sizeof(T)));
   if (b > by_lds) b = by_lds;
   if (b > cap) b = cap;
   return b < 1 ? 1 : b;
@@ -70,7 +61,6 @@ __device__ __forceinline__ int imod(int a, int n) {
 // h_m*dt/phihat_t((n - n0)/n_t); bins b_lo .. b_lo+nb-1 are kept per sensor.
 // ---------------------------------------------------------------------------
 constexpr int kTemporalThreads = 512;
-constexpr int kTemporalMaxV = 16;
 
 template <typename T>
 __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
@@ -90,7 +80,7 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
   const T w1 = has1 ? hw[m1] : T(0);
   const T* g0 = g + size_t(m0) * Nt;
   const T* g1 = g + size_t(has1 ? m1 : m0) * Nt;
-  staged_copy<kTemporalMaxV>(
+  staged_copy<kFftMaxV>(
       Nt, tid, nthr,
       [&](int n) {
         const T d = deap[n];
@@ -102,7 +92,7 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
         buf[lpos(pos)] = v;
       });
   __syncthreads();
-  fft_lds<T, kTemporalMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
+  fft_lds<T, kFftMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
   cx<T>* o0 = Gt + size_t(m0) * nb;
   cx<T>* o1 = Gt + size_t(m1) * nb;
   for (int i = tid; i < nb; i += nthr) {
@@ -164,7 +154,7 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
                                                 const int* __restrict__ tile_sens, const int* __restrict__ sbx,
                                                 const int* __restrict__ sby, const T* __restrict__ swx,
                                                 const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
-                                                int nchunks, cx<T>* __restrict__ U) {
+                                                int nchunks, int b_begin, int b_end, cx<T>* __restrict__ U) {
   constexpr int BC = kSpreadBins;
   constexpr int SB = kSpreadBatch;
   __shared__ int s_bx[SB], s_by[SB];
@@ -180,8 +170,8 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   const int px = txi * kSpreadTile + (lane & 15);
   const int prow0 = tyi * kSpreadTile + wave * 4;
   const int py = prow0 + (lane >> 4);
-  const int b0 = chunk * BC;
-  const int nbc = min(BC, nb - b0);
+  const int b0 = b_begin + chunk * BC;  // first bin of this group; U holds bins from b_begin on
+  const int nbc = min(BC, b_end - b0);
   cx<T> acc[BC];
   cx<T> cmp[KAHAN ? BC : 1];
 #pragma unroll
@@ -228,7 +218,7 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
     }
   }
   if (px < n_x && py < n_y) {
-    cx<T>* out = U + (size_t(b0) * n_y + py) * n_x + px;
+    cx<T>* out = U + (size_t(b0 - b_begin) * n_y + py) * n_x + px;
     const size_t slice = size_t(n_y) * n_x;
 #pragma unroll
     for (int b = 0; b < BC; ++b)
@@ -237,19 +227,19 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
 }
 
 template <typename T>
-hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t s) {
-  if (p.w_xy > kMaxW) return hipErrorInvalidValue;
-  const int nchunks = (p.nb + kSpreadBins - 1) / kSpreadBins;
+hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin, int b_end, hipStream_t s) {
+  if (p.w_xy > kMaxW || b_begin < 0 || b_end > p.nb || b_begin >= b_end) return hipErrorInvalidValue;
+  const int nchunks = (b_end - b_begin + kSpreadBins - 1) / kSpreadBins;
   const long long blocks = (long long)p.tiles_x * p.tiles_y * nchunks;
   if (p.kahan)
     hipLaunchKernelGGL((k_spread<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt), p.nb,
                        p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
-                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks,
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks, b_begin, b_end,
                        static_cast<cx<T>*>(U));
   else
     hipLaunchKernelGGL((k_spread<T, false>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt),
                        p.nb, p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
-                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks,
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks, b_begin, b_end,
                        static_cast<cx<T>*>(U));
   return hipGetLastError();
 }
@@ -258,31 +248,31 @@ hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t 
 // Stage 2: FFT along x of every grid row, keeping the Nx centred modes.
 // U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
 // ---------------------------------------------------------------------------
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
-                                                     FftDesc<T> fd, cx<T>* __restrict__ V) {
+                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_x = fd.n;
   const int bstride = lseq(n_x);
-  const int b = blockIdx.y;
+  const int b = b_begin + blockIdx.y;
   const int py0 = blockIdx.x * rows;
   const int nr = min(rows, n_y - py0);
-  const cx<T>* src = U + (size_t(b) * n_y + py0) * n_x;
+  const cx<T>* src = U + (size_t(b - b_begin) * n_y + py0) * n_x;
   const FastDiv div_nx(n_x), div_nr(nr);
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nr * n_x, tid, nthr, [&](int q) { return src[q]; },
       [&](int q, cx<T> v) {
         const int r = div_nx(q);
         buf[r * bstride + lpos(q - r * n_x)] = v;
       });
   __syncthreads();
-  fft_lds<T, MaxV<T>::v, false>(buf, fd, nr, bstride, tid, nthr);
+  fft_lds<T, kFftMaxV, false>(buf, fd, nr, bstride, tid, nthr);
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nr * Nx, tid, nthr,
       [&](int q) {
         const int jj = div_nr(q);
@@ -297,14 +287,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__
 }
 
 template <typename T>
-hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, hipStream_t s) {
-  const int rows = lds_batch<T>(p.n_x, 16);
+hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s) {
+  const int rows = fft_batch<T>(p.n_x, kFftThreads, 16);
   const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
+  if (size_t(rows) * p.n_x > size_t(kFftMaxV) * kFftThreads || size_t(rows) * p.Nx > size_t(kFftMaxV) * kFftThreads ||
+      b_begin < 0 || b_end > p.nb || b_begin >= b_end)
+    return hipErrorInvalidValue;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x<T>), lds);
   if (e != hipSuccess) return e;
-  dim3 grid((p.n_y + rows - 1) / rows, p.nb);
+  dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
   hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
-                     as_desc<T>(p.f_nx), static_cast<cx<T>*>(V));
+                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V));
   return hipGetLastError();
 }
 
@@ -326,7 +319,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
   const int b0 = blockIdx.x * bins;
   const int nbc = min(bins, nb - b0);
   const FastDiv div_ny(n_y), div_nbc(nbc);
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nbc * n_y, tid, nthr,
       [&](int q) {
         const int bi = div_ny(q);
@@ -337,10 +330,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
         buf[bi * bstride + lpos(q - bi * n_y)] = v;
       });
   __syncthreads();
-  fft_lds<T, MaxV<T>::v, false>(buf, fd, nbc, bstride, tid, nthr);
+  fft_lds<T, kFftMaxV, false>(buf, fd, nbc, bstride, tid, nthr);
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nbc * Ny, tid, nthr,
       [&](int q) {
         const int kk = div_nbc(q);
@@ -358,8 +351,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
 
 template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
-  const int bins = lds_batch<T>(p.n_y, 16);
+  const int bins = fft_batch<T>(p.n_y, kFftThreads, 16);
   const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  if (size_t(bins) * p.n_y > size_t(kFftMaxV) * kFftThreads || size_t(bins) * p.Ny > size_t(kFftMaxV) * kFftThreads)
+    return hipErrorInvalidValue;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y<T>), lds);
   if (e != hipSuccess) return e;
   dim3 grid((p.nb + bins - 1) / bins, p.Nx);
@@ -453,7 +448,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
   const int l0 = blockIdx.x * lchunk;
   const int nl = min(lchunk, Lh - l0);
   const FastDiv div_nl(nl);
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
       [&](int q) {
         const int jj = div_nl(q);
@@ -464,8 +459,8 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
   __syncthreads();
-  fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
-  staged_copy<MaxV<T>::v>(
+  fft_lds<T, kFftMaxV, true>(buf, fd, nl, bstride, tid, nthr);
+  staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
       [&](int q) {
         const int jj = div_nl(q);
@@ -489,7 +484,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
   const int nl = min(lchunk, Lh - l0);
   cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
   const FastDiv div_nl(nl);
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
       [&](int q) {
         const int kk = div_nl(q);
@@ -500,8 +495,8 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
   __syncthreads();
-  fft_lds<T, MaxV<T>::v, true>(buf, fd, nl, bstride, tid, nthr);
-  staged_copy<MaxV<T>::v>(
+  fft_lds<T, kFftMaxV, true>(buf, fd, nl, bstride, tid, nthr);
+  staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
       [&](int q) {
         const int kk = div_nl(q);
@@ -525,7 +520,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
   const long long r0 = (long long)blockIdx.x * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
   const FastDiv div_lh(Lh), div_nz(Nz);
-  staged_copy<MaxV<T>::v>(
+  staged_copy<kFftMaxV>(
       nr * Lh, tid, nthr, [&](int q) { return F[r0 * Lh + q]; },
       [&](int q, cx<T> v) {
         const int r = div_lh(q);
@@ -534,8 +529,8 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
         if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
       });
   __syncthreads();
-  fft_lds<T, MaxV<T>::v, true>(buf, fd, nr, bstride, tid, nthr);
-  staged_copy<MaxV<T>::v>(
+  fft_lds<T, kFftMaxV, true>(buf, fd, nr, bstride, tid, nthr);
+  staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr,
       [&](int q) {
         const int r = div_nz(q);
@@ -549,7 +544,7 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   cx<T>* F = static_cast<cx<T>*>(Fh);
   const int Lh = p.Nz / 2 + 1;
   {
-    const int lc = lds_batch<T>(p.Nx, 16);
+    const int lc = fft_batch<T>(p.Nx, kFftThreads, 16);
     const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_x<T>), lds);
     if (e != hipSuccess) return e;
@@ -559,7 +554,7 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   {
-    const int lc = lds_batch<T>(p.Ny, 16);
+    const int lc = fft_batch<T>(p.Ny, kFftThreads, 16);
     const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_y<T>), lds);
     if (e != hipSuccess) return e;
@@ -569,7 +564,7 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   {
-    const int rows = lds_batch<T>(p.Nz, 16);
+    const int rows = fft_batch<T>(p.Nz, kFftThreads, 16);
     const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds);
     if (e != hipSuccess) return e;
@@ -582,8 +577,8 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
 
 #define PATK_INSTANTIATE(T)                                                                     \
   template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, hipStream_t);         \
-  template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, hipStream_t);         \
-  template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, hipStream_t);         \
+  template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
+  template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);  \
   template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);         \
   template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, bool, hipStream_t);  \
   template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t);

@@ -25,6 +25,7 @@ struct DevPlan {
   int n_x = 0, n_y = 0, n_t = 0, n0 = 0, b_lo = 0, nb = 0;
   int w_xy = 0, w_t = 0, hdeg = 0;
   int tiles_x = 0, tiles_y = 0;
+  int chunk_bins = 0;          // bins per spread / x-FFT round (the grid buffer holds this many)
   bool kahan = false;
   double s_per_k = 0.0;        // c*dt*n_t/(2 pi): oversampled bin per unit |K|
   double kxu = 0, kyu = 0, kzu = 0;  // 2 pi/X, 2 pi/Y, 2 pi/Z
@@ -51,10 +52,12 @@ constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
 // Stage launchers; T = float or double. Buffers are device pointers.
 template <typename T>
 hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s);
+// Bins [b_begin, b_end) of the band: U holds only those bins (U[b - b_begin]),
+// V all bins.
 template <typename T>
-hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, hipStream_t s);
+hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin, int b_end, hipStream_t s);
 template <typename T>
-hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, hipStream_t s);
+hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s);
 template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s);
 // physical = true: F(K) as defined (sign (-1)^(j+k), no 1/V); false: the
