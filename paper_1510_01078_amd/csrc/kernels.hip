@@ -160,6 +160,9 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   __shared__ int s_bx[SB], s_by[SB];
   __shared__ T s_wx[SB * kMaxW], s_wy[SB * kMaxW];
   __shared__ cx<T> s_g[SB * BC];
+  // bin groups vary fastest: groups running together share one tile's sensor
+  // list and read whole per-sensor rows of Gt (measured faster on MI355X than
+  // ordering by tile)
   const int chunk = blockIdx.x % nchunks;
   const int tile = blockIdx.x / nchunks;
   const int tyi = tile / tiles_x;

@@ -105,16 +105,32 @@ def test_random_ragged(dev, precision, tol, kernel, w, sig):
 # Gaussian width 12 at oversampling 2 (and the Kaiser-Bessel default)
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("kernel,w", [("gaussian", 12), ("kaiser_bessel", 8)])
-def test_config_64x64(dev, kernel, w):
+# the benchmark's tuned setting: lateral sigma 1.5 / w 8, temporal sigma 1.25 / w 10
+TUNED = dict(kernel="kaiser_bessel", sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+
+
+@pytest.mark.parametrize("params", [dict(kernel="gaussian", width_xy=12, width_t=12),
+                                    dict(kernel="kaiser_bessel", width_xy=8, width_t=8), TUNED],
+                         ids=["gaussian12", "kb8", "tuned"])
+def test_config_64x64(dev, params):
     p = inputs.config_problem(1)
     _say("[gpu] 64x64 oracle ...")
     f_or, st = _oracle(p, "c1")
     for precision, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
-        _say(f"[gpu] 64x64 {precision} {kernel} w={w}")
-        f = _gpu(p, precision, kernel=kernel, width_xy=w, width_t=w)
+        _say(f"[gpu] 64x64 {precision} {params}")
+        f = _gpu(p, precision, **params)
         e = rel_l2(f, f_or)
-        _say(f"[gpu] 64x64 {precision} {kernel} w={w}: image rel-L2 {e:.3e}")
+        _say(f"[gpu] 64x64 {precision} {params}: image rel-L2 {e:.3e}")
+        assert e <= tol
+
+
+def test_tiny_tuned(dev):
+    p = inputs.config_problem(0)
+    f_or, _ = _oracle(p, "c0")
+    for precision, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+        f = _gpu(p, precision, **TUNED)
+        e = rel_l2(f, f_or)
+        _say(f"[gpu] tiny tuned {precision}: image rel-L2 {e:.3e}")
         assert e <= tol
 
 
@@ -133,3 +149,53 @@ def test_bitwise_repeatable(dev):
     torch.cuda.synchronize()
     pl.close()
     assert torch.equal(a, b)
+
+
+# --------------------------------------------------------------------------
+# headline size (128x128 sensors x 2048 samples -> 256^3) in the benchmark's
+# configuration: spectrum vs the oracle on sampled lateral x-modes, and the
+# image vs the oracle's inverse transform of the GPU spectrum
+# --------------------------------------------------------------------------
+
+def _full_from_half(H, nz):
+    """Natural-order full spectrum from the [j mod Nx][k mod Ny][l = 0..Nz/2]
+    half (F(-K) = conj F(K)); pure re-indexing for the oracle's inverse."""
+    nx, ny, _ = H.shape
+    full = np.zeros((nx, ny, nz), dtype=np.complex128)
+    for l in range(-(nz // 2), nz - nz // 2):
+        if l >= 0:
+            full[:, :, l % nz] = H[:, :, l]
+        else:
+            jj = (-np.arange(nx)) % nx
+            kk = (-np.arange(ny)) % ny
+            full[:, :, l % nz] = np.conj(H[jj][:, kk, -l])
+    # FFT order -> natural order on every axis
+    return np.fft.fftshift(full, axes=(0, 1, 2))
+
+
+def test_headline_size_sampled(dev):
+    from paper_1510_01078_amd import Plan
+    p = inputs.config_problem(2)
+    Nx, Ny, Nz = p.shape
+    X, Y, Z = p.extent
+    pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32", **TUNED)
+    g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, torch.float32)
+    _say("[gpu] headline size: spectrum and image")
+    H = pl.spectrum(g).cpu().numpy().astype(np.complex128)
+    f = pl.reconstruct(g).cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    pl.close()
+    rows = np.array([1, 77, 128, 131, 200, 255])          # natural-order x positions
+    kx, ky, kz = oracle.lattice(Nx, X), oracle.lattice(Ny, Y), oracle.lattice(Nz, Z)
+    G = oracle.stage_lateral(p.xy, p.h, p.g, p.dt, Nx, Ny, X, Y, j_index=rows)
+    S = oracle.stage_temporal(G, kx[rows], ky, kz, p.c, p.dt)
+    F = oracle.apply_weight(S, kx, ky, kz, p.c, j_index=rows)
+    lz = np.arange(Nz // 2 + 1)
+    ref = np.fft.ifftshift(F, axes=1)[:, :, (lz + Nz // 2) % Nz]
+    got = H[(rows - Nx // 2) % Nx]
+    e_spec = rel_l2(got, ref)
+    f_from_spec = oracle.inverse(_full_from_half(H, Nz), X, Y, Z)
+    e_img = rel_l2(f, f_from_spec)
+    _say(f"[gpu] headline: spectrum rel-L2 on {len(rows)} x-modes {e_spec:.3e}; image vs inverse of GPU spectrum {e_img:.3e}")
+    assert e_spec <= 1e-5
+    assert e_img <= 1e-5
