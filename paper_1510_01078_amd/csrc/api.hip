@@ -208,7 +208,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
     const double smin = dp.kzu * dp.s_per_k;
     const long blo = (long)std::floor(smin) - dp.w_t / 2;
     const long bhi = (long)std::floor(smax) + dp.w_t / 2 + 1;
-    if (bhi - blo + 1 > dp.n_t) return PAT_ERR_UNSUPPORTED;
+    if (bhi - blo + 1 > dp.n_t || blo <= -dp.n_t || bhi >= dp.n_t) return PAT_ERR_UNSUPPORTED;
     dp.b_lo = (int)blo;
     dp.nb = (int)(bhi - blo + 1);
   }

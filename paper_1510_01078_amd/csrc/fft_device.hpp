@@ -177,9 +177,22 @@ struct Dft<T, 5, INV> {
   }
 };
 
+// Ordering between the read and write phases of a pass: a work-group barrier,
+// or (when one wave owns the sequences) wave-local ordering of its LDS traffic.
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One radix-R Stockham pass over `batch` sequences; every thread holds at
 // most MAXV values, so batch*n <= MAXV*nthr is required (and batch*n < 2^16).
-template <typename T, int R, int MAXV, bool INV>
+template <typename T, int R, int MAXV, bool INV, bool WAVE = false>
 __device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int batch, int bstride,
                                               const cx<T>* __restrict__ tw, int tid, int nthr) {
   constexpr int K = (MAXV + R - 1) / R;
@@ -209,7 +222,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int
       Dft<T, R, INV>::run(v[it]);
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 #pragma unroll
   for (int it = 0; it < K; ++it) {
     const int idx = tid + it * nthr;
@@ -223,20 +236,23 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int
       for (int r = 0; r < R; ++r) dst[lpos(j0 + r * p)] = v[it][r];
     }
   }
-  __syncthreads();
+  fft_sync<WAVE>();
 }
 
-// Full transform (all passes). Callers must __syncthreads() after filling buf.
-template <typename T, int MAXV, bool INV>
+// Full transform (all passes). With WAVE = false the work-group's threads
+// cooperate on `batch` sequences and callers must __syncthreads() after
+// filling buf; with WAVE = true the 64 lanes of one wave (tid = lane,
+// nthr = 64) own the sequences and only wave-local ordering is used.
+template <typename T, int MAXV, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int batch, int bstride, int tid, int nthr) {
   for (int s = 0; s < fd.npass; ++s) {
     const FftPass ps = fd.pass[s];
     switch (ps.R) {
-      case 8: stockham_pass<T, 8, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 4: stockham_pass<T, 4, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 2: stockham_pass<T, 2, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 3: stockham_pass<T, 3, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      default: stockham_pass<T, 5, MAXV, INV>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 8: stockham_pass<T, 8, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 4: stockham_pass<T, 4, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 2: stockham_pass<T, 2, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 3: stockham_pass<T, 3, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      default: stockham_pass<T, 5, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
     }
   }
 }

@@ -32,6 +32,30 @@ static int fft_batch(int n, int nthr, int cap) {
   return b < 1 ? 1 : b;
 }
 
+// Transform the nseq sequences of length fd.n in LDS. Sequences of at most
+// 1024 points are each owned by one wave (no work-group barriers inside the
+// transform); longer ones use the whole work-group. Callers synchronise the
+// work-group before (after filling) and after (before reading).
+constexpr int kWaveFftMax = 1024;
+
+// FFT work-group shape: 256 threads, at most 8 sequences per group (measured
+// best on MI355X among 128-512 threads and 4-16 sequences, block or wave mode)
+struct FftCfg {
+  int threads = 256, cap = 8, wave = 0;
+};
+static FftCfg fft_cfg() { return FftCfg{}; }
+
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int nseq, int bstride, int tid, int nthr,
+                                          int wave_mode) {
+  if (wave_mode && fd.n <= kWaveFftMax) {
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    for (int q = wave; q < nseq; q += nwaves) fft_lds<T, 16, INV, true>(buf + q * bstride, fd, 1, bstride, lane, 64);
+  } else {
+    fft_lds<T, kFftMaxV, INV, false>(buf, fd, nseq, bstride, tid, nthr);
+  }
+}
+
 // Allow a kernel more than the default dynamic LDS when a launch needs it.
 static hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -49,11 +73,6 @@ static FftDesc<T> as_desc(const FftRaw& r) {
   return d;
 }
 
-__device__ __forceinline__ int imod(int a, int n) {
-  int r = a % n;
-  return r < 0 ? r + n : r;
-}
-
 // ---------------------------------------------------------------------------
 // Stage 0: temporal FFT per sensor (the equispaced half of eq. NER_NUFFT).
 // Two real traces share one complex FFT (re = sensor m0, im = sensor m1).
@@ -65,55 +84,65 @@ constexpr int kTemporalThreads = 512;
 template <typename T>
 __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
                                                              const T* __restrict__ hw, const T* __restrict__ deap,
-                                                             FftDesc<T> fd, int b_lo, int nb,
+                                                             FftDesc<T> fd, int b_lo, int nb, int pairs,
                                                              cx<T>* __restrict__ Gt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_t = fd.n;
-  const int m0 = 2 * blockIdx.x;
-  const int m1 = m0 + 1;
-  const bool has1 = m1 < M;
-  for (int q = tid; q < lseq(n_t); q += nthr) buf[q] = cx<T>{T(0), T(0)};
+  const int L = lseq(n_t);
+  const int mbase = 2 * pairs * blockIdx.x;  // first sensor of this group
+  const int np = min(pairs, (M - mbase + 1) / 2);
+  for (int q = tid; q < np * L; q += nthr) buf[q] = cx<T>{T(0), T(0)};
   __syncthreads();
-  const T w0 = hw[m0];
-  const T w1 = has1 ? hw[m1] : T(0);
-  const T* g0 = g + size_t(m0) * Nt;
-  const T* g1 = g + size_t(has1 ? m1 : m0) * Nt;
+  const FastDiv div_nt(Nt);
   staged_copy<kFftMaxV>(
-      Nt, tid, nthr,
-      [&](int n) {
+      np * Nt, tid, nthr,
+      [&](int q) {
+        const int pr = div_nt(q);
+        const int n = q - pr * Nt;
+        const int m0 = mbase + 2 * pr;
+        const bool has1 = m0 + 1 < M;
         const T d = deap[n];
-        return cx<T>{g0[n] * w0 * d, has1 ? g1[n] * w1 * d : T(0)};
+        const T a = g[size_t(m0) * Nt + n] * hw[m0] * d;
+        const T b = has1 ? g[size_t(m0 + 1) * Nt + n] * hw[m0 + 1] * d : T(0);
+        return cx<T>{a, b};
       },
-      [&](int n, cx<T> v) {
-        int pos = n - n0;
+      [&](int q, cx<T> v) {
+        const int pr = div_nt(q);
+        int pos = q - pr * Nt - n0;
         if (pos < 0) pos += n_t;
-        buf[lpos(pos)] = v;
+        buf[pr * L + lpos(pos)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
-  cx<T>* o0 = Gt + size_t(m0) * nb;
-  cx<T>* o1 = Gt + size_t(m1) * nb;
-  for (int i = tid; i < nb; i += nthr) {
-    const int b = b_lo + i;
-    const cx<T> z = buf[lpos(imod(b, n_t))];
-    const cx<T> zm = buf[lpos(imod(-b, n_t))];
+  fft_lds<T, kFftMaxV, false>(buf, fd, np, L, tid, nthr);
+  const FastDiv div_nb(nb);
+  for (int q = tid; q < np * nb; q += nthr) {
+    const int pr = div_nb(q);
+    const int i = q - pr * nb;
+    const int m0 = mbase + 2 * pr;
+    const int b = b_lo + i;  // -n_t < b < n_t (the band fits in n_t bins)
+    const int pb = b < 0 ? b + n_t : b;
+    const int mb = b > 0 ? n_t - b : -b;
+    const cx<T> z = buf[pr * L + lpos(pb)];
+    const cx<T> zm = buf[pr * L + lpos(mb)];
     // transform of the real part: (Z_b + conj Z_-b)/2; of the imaginary part: (Z_b - conj Z_-b)/(2i)
-    o0[i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-    if (has1) o1[i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+    Gt[size_t(m0) * nb + i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+    if (m0 + 1 < M) Gt[size_t(m0 + 1) * nb + i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
   }
 }
 
 template <typename T>
 hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s) {
-  const int blocks = (p.M + 1) / 2;
-  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
+  if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t) return hipErrorInvalidValue;
+  const int pairs = 1;  // one sensor pair per group measured fastest on MI355X
+  const int blocks = (p.M + 2 * pairs - 1) / (2 * pairs);
+  const size_t lds = size_t(pairs) * lseq(p.n_t) * sizeof(cx<T>);
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T>), lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
                      static_cast<const T*>(p.hw), static_cast<const T*>(p.deap), as_desc<T>(p.f_nt), p.b_lo, p.nb,
-                     static_cast<cx<T>*>(Gt));
+                     pairs, static_cast<cx<T>*>(Gt));
   return hipGetLastError();
 }
 
@@ -186,23 +215,41 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   for (int qb = q_begin; qb < q_end; qb += SB) {
     const int nq = min(SB, q_end - qb);
     __syncthreads();  // the previous batch has been consumed
-    for (int t = tid; t < nq; t += 256) {
-      const int sidx = tile_sens[qb + t];
-      s_bx[t] = sbx[sidx];
-      s_by[t] = sby[sidx];
-    }
-    for (int t = tid; t < nq * kMaxW; t += 256) {
-      const int qi = t >> 4, ti = t & (kMaxW - 1);
-      if (ti < w) {
+    {
+      // four threads per staged sensor: one read of the sensor index, then every
+      // table and bin load of that sensor issued together
+      static_assert(SB * 4 == 256 && kMaxW == 16 && BC == 16, "staging layout");
+      const int qi = tid >> 2, r = tid & 3;
+      if (qi < nq) {
         const int sidx = tile_sens[qb + qi];
-        s_wx[t] = swx[sidx * w + ti];
-        s_wy[t] = swy[sidx * w + ti];
+        const T* wxs = swx + size_t(sidx) * w;
+        const T* wys = swy + size_t(sidx) * w;
+        const cx<T>* gs = Gt + size_t(sidx) * nb + b0;
+        T vx[4], vy[4];
+        cx<T> vg[4];
+        int bxv = 0, byv = 0;
+        if (r == 0) {
+          bxv = sbx[sidx];
+          byv = sby[sidx];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = r * 4 + i;
+          vx[i] = e < w ? wxs[e] : T(0);
+          vy[i] = e < w ? wys[e] : T(0);
+          vg[i] = e < nbc ? gs[e] : cx<T>{T(0), T(0)};
+        }
+        if (r == 0) {
+          s_bx[qi] = bxv;
+          s_by[qi] = byv;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          s_wx[qi * kMaxW + r * 4 + i] = vx[i];
+          s_wy[qi * kMaxW + r * 4 + i] = vy[i];
+          s_g[qi * BC + r * 4 + i] = vg[i];
+        }
       }
-    }
-    for (int t = tid; t < nq * BC; t += 256) {
-      const int qi = t / BC, bi = t - qi * BC;
-      const int sidx = tile_sens[qb + qi];
-      s_g[t] = bi < nbc ? Gt[size_t(sidx) * nb + b0 + bi] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     for (int qi = 0; qi < nq; ++qi) {
@@ -251,11 +298,11 @@ hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin,
 // Stage 2: FFT along x of every grid row, keeping the Nx centred modes.
 // U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
 // ---------------------------------------------------------------------------
-constexpr int kFftThreads = 512;
+constexpr int kFftThreads = 256;
 
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
-                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V) {
+                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -273,7 +320,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__
         buf[r * bstride + lpos(q - r * n_x)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, false>(buf, fd, nr, bstride, tid, nthr);
+  fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
+  __syncthreads();
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
   staged_copy<kFftMaxV>(
       nr * Nx, tid, nthr,
@@ -291,16 +339,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__
 
 template <typename T>
 hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s) {
-  const int rows = fft_batch<T>(p.n_x, kFftThreads, 16);
+  const FftCfg cfg = fft_cfg();
+  const int rows = fft_batch<T>(p.n_x, cfg.threads, cfg.cap);
   const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
-  if (size_t(rows) * p.n_x > size_t(kFftMaxV) * kFftThreads || size_t(rows) * p.Nx > size_t(kFftMaxV) * kFftThreads ||
+  if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
       b_begin < 0 || b_end > p.nb || b_begin >= b_end)
     return hipErrorInvalidValue;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x<T>), lds);
   if (e != hipSuccess) return e;
   dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
-  hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
-                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V));
+  hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
+                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
   return hipGetLastError();
 }
 
@@ -312,7 +361,7 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                                      const T* __restrict__ dcx, const T* __restrict__ dcy,
-                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh) {
+                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -333,7 +382,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
         buf[bi * bstride + lpos(q - bi * n_y)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, false>(buf, fd, nbc, bstride, tid, nthr);
+  fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
+  __syncthreads();
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
   staged_copy<kFftMaxV>(
@@ -354,16 +404,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
 
 template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
-  const int bins = fft_batch<T>(p.n_y, kFftThreads, 16);
+  const FftCfg cfg = fft_cfg();
+  const int bins = fft_batch<T>(p.n_y, cfg.threads, cfg.cap);
   const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
-  if (size_t(bins) * p.n_y > size_t(kFftMaxV) * kFftThreads || size_t(bins) * p.Ny > size_t(kFftMaxV) * kFftThreads)
+  if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y<T>), lds);
   if (e != hipSuccess) return e;
   dim3 grid((p.nb + bins - 1) / bins, p.Nx);
-  hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(kFftThreads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
+  hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
                      bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                     static_cast<cx<T>*>(Gh));
+                     static_cast<cx<T>*>(Gh), cfg.wave);
   return hipGetLastError();
 }
 
@@ -441,7 +492,7 @@ hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, bool physic
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
-                                                      FftDesc<T> fd) {
+                                                      FftDesc<T> fd, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -462,7 +513,8 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, true>(buf, fd, nl, bstride, tid, nthr);
+  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
       [&](int q) {
@@ -476,7 +528,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd) {
+__global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -498,7 +550,8 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, true>(buf, fd, nl, bstride, tid, nthr);
+  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
       [&](int q) {
@@ -513,7 +566,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
 
 template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
-                                                     FftDesc<T> fd, T* __restrict__ f) {
+                                                     FftDesc<T> fd, T* __restrict__ f, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -532,7 +585,8 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
         if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, true>(buf, fd, nr, bstride, tid, nthr);
+  fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
+  __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr,
       [&](int q) {
@@ -546,34 +600,35 @@ template <typename T>
 hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   cx<T>* F = static_cast<cx<T>*>(Fh);
   const int Lh = p.Nz / 2 + 1;
+  const FftCfg cfg = fft_cfg();
   {
-    const int lc = fft_batch<T>(p.Nx, kFftThreads, 16);
+    const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
     const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_x<T>), lds);
     if (e != hipSuccess) return e;
     dim3 grid((Lh + lc - 1) / lc, p.Ny);
-    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(kFftThreads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx));
+    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx), cfg.wave);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
-    const int lc = fft_batch<T>(p.Ny, kFftThreads, 16);
+    const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
     const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_y<T>), lds);
     if (e != hipSuccess) return e;
     dim3 grid((Lh + lc - 1) / lc, p.Nx);
-    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(kFftThreads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny));
+    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(cfg.threads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny), cfg.wave);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   {
-    const int rows = fft_batch<T>(p.Nz, kFftThreads, 16);
+    const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
     const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds);
     if (e != hipSuccess) return e;
     const long long nrows = (long long)p.Nx * p.Ny;
-    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(kFftThreads), lds, s, F, nrows,
-                       rows, as_desc<T>(p.f_Nz), f);
+    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, F, nrows,
+                       rows, as_desc<T>(p.f_Nz), f, cfg.wave);
   }
   return hipGetLastError();
 }
