@@ -70,6 +70,32 @@ def stage_bytes(plan, p, eb):
     ]
 
 
+def recorded_traffic(args):
+    """HBM bytes per spread launch from the committed FETCH_SIZE/WRITE_SIZE
+    summary, or None when no record matches this workload or the spread
+    kernel's source has changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "k_spread_traffic_*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith("record:"):
+                    continue
+                rec = dict(kv.split("=", 1) for kv in line.split()[1:])
+                src = os.path.join(ROOT, rec["source"])
+                if not os.path.exists(src):
+                    continue
+                with open(src, "rb") as sf:
+                    digest = hashlib.sha256(sf.read()).hexdigest()
+                same = (digest == rec["sha256"] and int(rec["config"]) == args.config
+                        and rec["precision"] == args.precision and rec["kernel_kind"] == args.kernel
+                        and float(rec["sigma_xy"]) == args.sigma_xy and int(rec["width_xy"]) == args.width_xy
+                        and float(rec["sigma_t"]) == args.sigma_t and int(rec["width_t"]) == args.width_t)
+                if same:
+                    return int(rec["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
     """Time the FP64 oracle on `nsample` lateral x-modes (all y-modes, all
     depths), extrapolate to the full grid (plus the full inverse transform),
@@ -195,7 +221,7 @@ def main():
     spread_bytes_launch = sb[1] / rounds
     achieved = spread_bytes_launch / (spread_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_spread",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args), "kernel": "k_spread",
                 "bytes_per_launch": int(spread_bytes_launch), "ms_per_launch": round(spread_ms, 5),
                 "launches_per_step": rounds}
 

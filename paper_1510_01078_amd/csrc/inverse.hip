@@ -1,0 +1,164 @@
+// Equispaced inverse 3-D FFT of the weighted spectrum (the last step of the
+// NEDNER list in Section 3).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_common.hpp"
+
+namespace patk {
+
+// ---------------------------------------------------------------------------
+// Stage 5: equispaced inverse 3-D FFT (step 3 of the NEDNER list) on the
+// half spectrum Fh[jj][kk][l], l = 0..Nz/2: in-place inverse transforms
+// along x and along y, then a complex-to-real transform along z.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
+                                                      FftDesc<T> fd, int wm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Nx = fd.n;
+  const int bstride = lseq(Nx);
+  const int kk = blockIdx.y;
+  const int l0 = blockIdx.x * lchunk;
+  const int nl = min(lchunk, Lh - l0);
+  const FastDiv div_nl(nl);
+  staged_copy<kFftMaxV>(
+      nl * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nl(q);
+        return F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nl(q);
+        buf[(q - jj * nl) * bstride + lpos(jj)] = v;
+      });
+  __syncthreads();
+  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nl * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nl(q);
+        return buf[(q - jj * nl) * bstride + lpos(jj)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nl(q);
+        F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)] = v;
+      });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Ny = fd.n;
+  const int bstride = lseq(Ny);
+  const int jj = blockIdx.y;
+  const int l0 = blockIdx.x * lchunk;
+  const int nl = min(lchunk, Lh - l0);
+  cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
+  const FastDiv div_nl(nl);
+  staged_copy<kFftMaxV>(
+      nl * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nl(q);
+        return base[size_t(kk) * Lh + (q - kk * nl)];
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nl(q);
+        buf[(q - kk * nl) * bstride + lpos(kk)] = v;
+      });
+  __syncthreads();
+  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nl * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nl(q);
+        return buf[(q - kk * nl) * bstride + lpos(kk)];
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nl(q);
+        base[size_t(kk) * Lh + (q - kk * nl)] = v;
+      });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
+                                                     FftDesc<T> fd, T* __restrict__ f, int wm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Nz = fd.n;
+  const int Lh = Nz / 2 + 1;
+  const int bstride = lseq(Nz);
+  const long long r0 = (long long)blockIdx.x * rows;
+  const int nr = (int)min((long long)rows, nrows - r0);
+  const FastDiv div_lh(Lh), div_nz(Nz);
+  staged_copy<kFftMaxV>(
+      nr * Lh, tid, nthr, [&](int q) { return F[r0 * Lh + q]; },
+      [&](int q, cx<T> v) {
+        const int r = div_lh(q);
+        const int l = q - r * Lh;
+        buf[r * bstride + lpos(l)] = v;
+        if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
+      });
+  __syncthreads();
+  fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nr * Nz, tid, nthr,
+      [&](int q) {
+        const int r = div_nz(q);
+        return buf[r * bstride + lpos(q - r * Nz)].x;
+      },
+      [&](int q, T v) { f[r0 * Nz + q] = v; });
+}
+
+template <typename T>
+hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
+  cx<T>* F = static_cast<cx<T>*>(Fh);
+  const int Lh = p.Nz / 2 + 1;
+  const FftCfg cfg = fft_cfg();
+  {
+    const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
+    const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_x<T>), lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((Lh + lc - 1) / lc, p.Ny);
+    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx), cfg.wave);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
+    const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_y<T>), lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((Lh + lc - 1) / lc, p.Nx);
+    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(cfg.threads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny), cfg.wave);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
+    const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds);
+    if (e != hipSuccess) return e;
+    const long long nrows = (long long)p.Nx * p.Ny;
+    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, F, nrows,
+                       rows, as_desc<T>(p.f_Nz), f, cfg.wave);
+  }
+  return hipGetLastError();
+}
+
+#define PATK_INST(T) template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t);
+PATK_INST(float)
+PATK_INST(double)
+#undef PATK_INST
+
+}  // namespace patk

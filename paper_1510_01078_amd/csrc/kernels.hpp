@@ -1,4 +1,15 @@
-// Interface between the host plan code and the gfx950 kernels.
+// Interface between the host plan code and the gfx950 stage kernels of the
+// NEDNER-NUFFT reconstruction (Section 3: a non-equispaced-range NUFFT in
+// time, a non-equispaced-data NUFFT over the sensor plane, then an
+// equispaced inverse FFT).
+//
+// Order of the steps on the device. The temporal transform's equispaced part
+// (deapodise, zero-pad, FFT) runs first, per sensor; the lateral NUFFT then
+// runs once per kept temporal bin; the temporal interpolation at
+// omega(K) = c|K| runs last, per lateral mode. This is the paper's
+// composition with the two linear maps on different indices applied in the
+// other order, which lets the lateral grid be built only for the band of
+// temporal bins that the interpolation reads.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>

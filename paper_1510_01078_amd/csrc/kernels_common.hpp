@@ -1,0 +1,68 @@
+// Helpers shared by the gfx950 stage kernels: FFT work-group shape, the
+// in-LDS transform of a batch of sequences, dynamic-LDS opt-in and the
+// device view of an FFT plan.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+#include "kernels.hpp"
+
+namespace patk {
+
+constexpr int kFftMaxV = 16;    // values per thread in the FFT kernels
+constexpr int kFftThreads = 256; // threads per FFT work-group
+
+// Sequences of length n per FFT work-group of nthr threads: at most kFftMaxV
+// values per thread, at most `cap`, and (when possible) within 80 KiB of LDS
+// so two work-groups share a CU.
+template <typename T>
+static inline int fft_batch(int n, int nthr, int cap) {
+  int b = kFftMaxV * nthr / n;
+  const int by_lds = int(81920 / (size_t(lseq(n)) * 2 * sizeof(T)));
+  if (b > by_lds) b = by_lds;
+  if (b > cap) b = cap;
+  return b < 1 ? 1 : b;
+}
+
+// Transform the nseq sequences of length fd.n in LDS. Sequences of at most
+// 1024 points are each owned by one wave (no work-group barriers inside the
+// transform); longer ones use the whole work-group. Callers synchronise the
+// work-group before (after filling) and after (before reading).
+constexpr int kWaveFftMax = 1024;
+
+// FFT work-group shape: 256 threads, at most 8 sequences per group (measured
+// best on MI355X among 128-512 threads and 4-16 sequences, block or wave mode)
+struct FftCfg {
+  int threads = 256, cap = 8, wave = 0;
+};
+static inline FftCfg fft_cfg() { return FftCfg{}; }
+
+template <typename T, bool INV>
+__device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int nseq, int bstride, int tid, int nthr,
+                                          int wave_mode) {
+  if (wave_mode && fd.n <= kWaveFftMax) {
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+    for (int q = wave; q < nseq; q += nwaves) fft_lds<T, 16, INV, true>(buf + q * bstride, fd, 1, bstride, lane, 64);
+  } else {
+    fft_lds<T, kFftMaxV, INV, false>(buf, fd, nseq, bstride, tid, nthr);
+  }
+}
+
+// Allow a kernel more than the default dynamic LDS when a launch needs it.
+static inline hipError_t allow_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename T>
+static inline FftDesc<T> as_desc(const FftRaw& r) {
+  FftDesc<T> d;
+  static_assert(sizeof(FftPass) == sizeof(FftPassRaw), "pass layout");
+  d.n = r.n;
+  d.npass = r.npass;
+  d.pass = static_cast<const FftPass*>(r.dpass);
+  d.tw = static_cast<const cx<T>*>(r.tw);
+  return d;
+}
+
+}  // namespace patk

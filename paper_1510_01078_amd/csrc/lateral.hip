@@ -1,0 +1,140 @@
+// Equispaced part of the lateral NUFFT (Section 3.2): FFTs of the
+// oversampled grid along x and y, cropping and deconvolution.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_common.hpp"
+
+namespace patk {
+
+// ---------------------------------------------------------------------------
+// Stage 2: FFT along x of every grid row, keeping the Nx centred modes.
+// U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
+                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_x = fd.n;
+  const int bstride = lseq(n_x);
+  const int b = b_begin + blockIdx.y;
+  const int py0 = blockIdx.x * rows;
+  const int nr = min(rows, n_y - py0);
+  const cx<T>* src = U + (size_t(b - b_begin) * n_y + py0) * n_x;
+  const FastDiv div_nx(n_x), div_nr(nr);
+  staged_copy<kFftMaxV>(
+      nr * n_x, tid, nthr, [&](int q) { return src[q]; },
+      [&](int q, cx<T> v) {
+        const int r = div_nx(q);
+        buf[r * bstride + lpos(q - r * n_x)] = v;
+      });
+  __syncthreads();
+  fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
+  __syncthreads();
+  cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
+  staged_copy<kFftMaxV>(
+      nr * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nr(q);
+        const int r = q - jj * nr;
+        const int j = jj < Nx / 2 ? jj : jj - Nx;
+        return buf[r * bstride + lpos(j < 0 ? j + n_x : j)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nr(q);
+        dst[size_t(jj) * n_y + (q - jj * nr)] = v;
+      });
+}
+
+template <typename T>
+hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s) {
+  const FftCfg cfg = fft_cfg();
+  const int rows = fft_batch<T>(p.n_x, cfg.threads, cfg.cap);
+  const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
+  if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
+      b_begin < 0 || b_end > p.nb || b_begin >= b_end)
+    return hipErrorInvalidValue;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x<T>), lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
+  hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
+                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Stage 3: FFT along y, keep the Ny centred modes, divide by the window
+// transform in x and y (eq. NED_NUFFT's 1/Psi_j), and transpose so the bins
+// of each lateral mode are contiguous: V[b][jj][py] -> Gh[jj][kk][b].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
+                                                     const T* __restrict__ dcx, const T* __restrict__ dcy,
+                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_y = fd.n;
+  const int bstride = lseq(n_y);
+  const int jj = blockIdx.y;
+  const int b0 = blockIdx.x * bins;
+  const int nbc = min(bins, nb - b0);
+  const FastDiv div_ny(n_y), div_nbc(nbc);
+  staged_copy<kFftMaxV>(
+      nbc * n_y, tid, nthr,
+      [&](int q) {
+        const int bi = div_ny(q);
+        return V[(size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y)];
+      },
+      [&](int q, cx<T> v) {
+        const int bi = div_ny(q);
+        buf[bi * bstride + lpos(q - bi * n_y)] = v;
+      });
+  __syncthreads();
+  fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
+  __syncthreads();
+  const T cxj = dcx[jj];
+  cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
+  staged_copy<kFftMaxV>(
+      nbc * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nbc(q);
+        const int bi = q - kk * nbc;
+        const int k = kk < Ny / 2 ? kk : kk - Ny;
+        const T sc = cxj * dcy[kk];
+        const cx<T> v = buf[bi * bstride + lpos(k < 0 ? k + n_y : k)];
+        return cx<T>{v.x * sc, v.y * sc};
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nbc(q);
+        dst[size_t(kk) * nb + (q - kk * nbc)] = v;
+      });
+}
+
+template <typename T>
+hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
+  const FftCfg cfg = fft_cfg();
+  const int bins = fft_batch<T>(p.n_y, cfg.threads, cfg.cap);
+  const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
+    return hipErrorInvalidValue;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y<T>), lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+  hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
+                     bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
+                     static_cast<cx<T>*>(Gh), cfg.wave);
+  return hipGetLastError();
+}
+
+#define PATK_INST(T)                                                                    \
+  template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
+  template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);
+PATK_INST(float)
+PATK_INST(double)
+#undef PATK_INST
+
+}  // namespace patk

@@ -1,0 +1,164 @@
+// Lateral gridding of the non-equispaced-data NUFFT over the sensor plane
+// (Section 3.2), one chunk of temporal bins at a time.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_common.hpp"
+
+namespace patk {
+
+// ---------------------------------------------------------------------------
+// Stage 1: lateral spreading (the gridding of eq. NED_NUFFT), one chunk of
+// temporal bins at a time. Output-driven and atomic-free: a work-group owns a
+// 16x16 tile of the oversampled grid (four waves, each a 16x4 patch) and
+// every lane owns one grid point, accumulating in registers the
+// contributions of the tile's sensor list in list order (deterministic).
+// The list is staged through LDS in batches (sensor footprint origin,
+// per-axis weights, the chunk's bin values), so the inner loop reads only
+// LDS: the bin values are wave-uniform broadcasts and the lane's weight is
+// wx[tx]*wy[ty] (0 outside the footprint).
+// ---------------------------------------------------------------------------
+constexpr int kSpreadBins = 16;
+constexpr int kSpreadBatch = 64;
+constexpr int kMaxW = 16;
+
+template <typename T, bool KAHAN>
+__device__ __forceinline__ void accum(cx<T>& a, cx<T>& c, T wt, cx<T> g) {
+  if (KAHAN) {
+    const T yr = wt * g.x - c.x;
+    const T tr = a.x + yr;
+    c.x = (tr - a.x) - yr;
+    a.x = tr;
+    const T yi = wt * g.y - c.y;
+    const T ti = a.y + yi;
+    c.y = (ti - a.y) - yi;
+    a.y = ti;
+  } else {
+    a.x += wt * g.x;
+    a.y += wt * g.y;
+  }
+}
+
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
+                                                const int* __restrict__ tile_sens, const int* __restrict__ sbx,
+                                                const int* __restrict__ sby, const T* __restrict__ swx,
+                                                const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
+                                                int nchunks, int b_begin, int b_end, cx<T>* __restrict__ U) {
+  constexpr int BC = kSpreadBins;
+  constexpr int SB = kSpreadBatch;
+  __shared__ int s_bx[SB], s_by[SB];
+  __shared__ T s_wx[SB * kMaxW], s_wy[SB * kMaxW];
+  __shared__ cx<T> s_g[SB * BC];
+  // bin groups vary fastest: groups running together share one tile's sensor
+  // list and read whole per-sensor rows of Gt (measured faster on MI355X than
+  // ordering by tile)
+  const int chunk = blockIdx.x % nchunks;
+  const int tile = blockIdx.x / nchunks;
+  const int tyi = tile / tiles_x;
+  const int txi = tile - tyi * tiles_x;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int px = txi * kSpreadTile + (lane & 15);
+  const int prow0 = tyi * kSpreadTile + wave * 4;
+  const int py = prow0 + (lane >> 4);
+  const int b0 = b_begin + chunk * BC;  // first bin of this group; U holds bins from b_begin on
+  const int nbc = min(BC, b_end - b0);
+  cx<T> acc[BC];
+  cx<T> cmp[KAHAN ? BC : 1];
+#pragma unroll
+  for (int b = 0; b < BC; ++b) acc[b] = cx<T>{T(0), T(0)};
+#pragma unroll
+  for (int b = 0; b < (KAHAN ? BC : 1); ++b) cmp[b] = cx<T>{T(0), T(0)};
+  const int q_begin = tile_off[tile];
+  const int q_end = tile_off[tile + 1];
+  for (int qb = q_begin; qb < q_end; qb += SB) {
+    const int nq = min(SB, q_end - qb);
+    __syncthreads();  // the previous batch has been consumed
+    {
+      // four threads per staged sensor: one read of the sensor index, then every
+      // table and bin load of that sensor issued together
+      static_assert(SB * 4 == 256 && kMaxW == 16 && BC == 16, "staging layout");
+      const int qi = tid >> 2, r = tid & 3;
+      if (qi < nq) {
+        const int sidx = tile_sens[qb + qi];
+        const T* wxs = swx + size_t(sidx) * w;
+        const T* wys = swy + size_t(sidx) * w;
+        const cx<T>* gs = Gt + size_t(sidx) * nb + b0;
+        T vx[4], vy[4];
+        cx<T> vg[4];
+        int bxv = 0, byv = 0;
+        if (r == 0) {
+          bxv = sbx[sidx];
+          byv = sby[sidx];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int e = r * 4 + i;
+          vx[i] = e < w ? wxs[e] : T(0);
+          vy[i] = e < w ? wys[e] : T(0);
+          vg[i] = e < nbc ? gs[e] : cx<T>{T(0), T(0)};
+        }
+        if (r == 0) {
+          s_bx[qi] = bxv;
+          s_by[qi] = byv;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          s_wx[qi * kMaxW + r * 4 + i] = vx[i];
+          s_wy[qi * kMaxW + r * 4 + i] = vy[i];
+          s_g[qi * BC + r * 4 + i] = vg[i];
+        }
+      }
+    }
+    __syncthreads();
+    for (int qi = 0; qi < nq; ++qi) {
+      const int by = s_by[qi];
+      int d0 = prow0 - by;
+      if (d0 < 0) d0 += n_y;
+      if (!(d0 < w || d0 + 3 >= n_y)) continue;  // footprint misses this wave's four rows
+      int tx = px - s_bx[qi];
+      if (tx < 0) tx += n_x;
+      int ty = py - by;
+      if (ty < 0) ty += n_y;
+      const T wt = (tx < w && ty < w) ? s_wx[qi * kMaxW + tx] * s_wy[qi * kMaxW + ty] : T(0);
+      const cx<T>* gq = s_g + qi * BC;
+#pragma unroll
+      for (int b = 0; b < BC; ++b) accum<T, KAHAN>(acc[b], cmp[KAHAN ? b : 0], wt, gq[b]);
+    }
+  }
+  if (px < n_x && py < n_y) {
+    cx<T>* out = U + (size_t(b0 - b_begin) * n_y + py) * n_x + px;
+    const size_t slice = size_t(n_y) * n_x;
+#pragma unroll
+    for (int b = 0; b < BC; ++b)
+      if (b < nbc) out[b * slice] = acc[b];
+  }
+}
+
+template <typename T>
+hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin, int b_end, hipStream_t s) {
+  if (p.w_xy > kMaxW || b_begin < 0 || b_end > p.nb || b_begin >= b_end) return hipErrorInvalidValue;
+  const int nchunks = (b_end - b_begin + kSpreadBins - 1) / kSpreadBins;
+  const long long blocks = (long long)p.tiles_x * p.tiles_y * nchunks;
+  if (p.kahan)
+    hipLaunchKernelGGL((k_spread<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt), p.nb,
+                       p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks, b_begin, b_end,
+                       static_cast<cx<T>*>(U));
+  else
+    hipLaunchKernelGGL((k_spread<T, false>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt),
+                       p.nb, p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
+                       static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks, b_begin, b_end,
+                       static_cast<cx<T>*>(U));
+  return hipGetLastError();
+}
+
+#define PATK_INST(T) template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);
+PATK_INST(float)
+PATK_INST(double)
+#undef PATK_INST
+
+}  // namespace patk

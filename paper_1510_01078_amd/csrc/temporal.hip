@@ -1,0 +1,89 @@
+// Temporal stage of the reconstruction: the equispaced part of the
+// non-equispaced-range NUFFT in time (Section 3.1), per sensor.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels_common.hpp"
+
+namespace patk {
+
+// ---------------------------------------------------------------------------
+// Stage 0: temporal FFT per sensor (the equispaced half of eq. NER_NUFFT).
+// Two real traces share one complex FFT (re = sensor m0, im = sensor m1).
+// Sample n sits at index (n - n0) mod n_t after multiplication by
+// h_m*dt/phihat_t((n - n0)/n_t); bins b_lo .. b_lo+nb-1 are kept per sensor.
+// ---------------------------------------------------------------------------
+constexpr int kTemporalThreads = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
+                                                             const T* __restrict__ hw, const T* __restrict__ deap,
+                                                             FftDesc<T> fd, int b_lo, int nb, int pairs,
+                                                             cx<T>* __restrict__ Gt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_t = fd.n;
+  const int L = lseq(n_t);
+  const int mbase = 2 * pairs * blockIdx.x;  // first sensor of this group
+  const int np = min(pairs, (M - mbase + 1) / 2);
+  for (int q = tid; q < np * L; q += nthr) buf[q] = cx<T>{T(0), T(0)};
+  __syncthreads();
+  const FastDiv div_nt(Nt);
+  staged_copy<kFftMaxV>(
+      np * Nt, tid, nthr,
+      [&](int q) {
+        const int pr = div_nt(q);
+        const int n = q - pr * Nt;
+        const int m0 = mbase + 2 * pr;
+        const bool has1 = m0 + 1 < M;
+        const T d = deap[n];
+        const T a = g[size_t(m0) * Nt + n] * hw[m0] * d;
+        const T b = has1 ? g[size_t(m0 + 1) * Nt + n] * hw[m0 + 1] * d : T(0);
+        return cx<T>{a, b};
+      },
+      [&](int q, cx<T> v) {
+        const int pr = div_nt(q);
+        int pos = q - pr * Nt - n0;
+        if (pos < 0) pos += n_t;
+        buf[pr * L + lpos(pos)] = v;
+      });
+  __syncthreads();
+  fft_lds<T, kFftMaxV, false>(buf, fd, np, L, tid, nthr);
+  const FastDiv div_nb(nb);
+  for (int q = tid; q < np * nb; q += nthr) {
+    const int pr = div_nb(q);
+    const int i = q - pr * nb;
+    const int m0 = mbase + 2 * pr;
+    const int b = b_lo + i;  // -n_t < b < n_t (the band fits in n_t bins)
+    const int pb = b < 0 ? b + n_t : b;
+    const int mb = b > 0 ? n_t - b : -b;
+    const cx<T> z = buf[pr * L + lpos(pb)];
+    const cx<T> zm = buf[pr * L + lpos(mb)];
+    // transform of the real part: (Z_b + conj Z_-b)/2; of the imaginary part: (Z_b - conj Z_-b)/(2i)
+    Gt[size_t(m0) * nb + i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+    if (m0 + 1 < M) Gt[size_t(m0 + 1) * nb + i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+  }
+}
+
+template <typename T>
+hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s) {
+  if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t) return hipErrorInvalidValue;
+  const int pairs = 1;  // one sensor pair per group measured fastest on MI355X
+  const int blocks = (p.M + 2 * pairs - 1) / (2 * pairs);
+  const size_t lds = size_t(pairs) * lseq(p.n_t) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
+                     static_cast<const T*>(p.hw), static_cast<const T*>(p.deap), as_desc<T>(p.f_nt), p.b_lo, p.nb,
+                     pairs, static_cast<cx<T>*>(Gt));
+  return hipGetLastError();
+}
+
+#define PATK_INST(T) template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, hipStream_t);
+PATK_INST(float)
+PATK_INST(double)
+#undef PATK_INST
+
+}  // namespace patk
