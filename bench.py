@@ -70,7 +70,7 @@ def stage_bytes(plan, p, eb):
     ]
 
 
-def recorded_traffic(args):
+def recorded_traffic(args, band_bins):
     """HBM bytes per spread launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when no record matches this workload or the spread
     kernel's source has changed since the counters were taken."""
@@ -90,7 +90,8 @@ def recorded_traffic(args):
                 same = (digest == rec["sha256"] and int(rec["config"]) == args.config
                         and rec["precision"] == args.precision and rec["kernel_kind"] == args.kernel
                         and float(rec["sigma_xy"]) == args.sigma_xy and int(rec["width_xy"]) == args.width_xy
-                        and float(rec["sigma_t"]) == args.sigma_t and int(rec["width_t"]) == args.width_t)
+                        and float(rec["sigma_t"]) == args.sigma_t and int(rec["width_t"]) == args.width_t
+                        and int(rec.get("band_bins", -1)) == band_bins)
                 if same:
                     return int(rec["traffic_bytes_per_launch"])
     return None
@@ -221,7 +222,7 @@ def main():
     spread_bytes_launch = sb[1] / rounds
     achieved = spread_bytes_launch / (spread_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args), "kernel": "k_spread",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args, plan.info["band_bins"]), "kernel": "k_spread",
                 "bytes_per_launch": int(spread_bytes_launch), "ms_per_launch": round(spread_ms, 5),
                 "launches_per_step": rounds}
 
@@ -247,6 +248,31 @@ def main():
         "stages": stages,
         "cpu_baseline": None,
     }
+    # the forward model and its adjoint on the same plan and traces (timed the
+    # same way; image input = the reconstruction just computed)
+    ops = {}
+    fwd_names = ["temporal_t", "interp", "lateral_fft_x_t", "lateral_fft_y_t", "scatter", "forward_fft3d"]
+    for name, call, snames in (("adjoint", lambda: plan.adjoint(g, out=out_adj), names),
+                               ("forward", lambda: plan.forward(out, out=g_fwd), fwd_names)):
+        if name == "adjoint":
+            out_adj = torch.empty_like(out)
+        else:
+            g_fwd = torch.empty_like(g)
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize(dev)
+        plan.timing_begin(args.steps)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize(dev)
+        el = time.perf_counter() - t0
+        sm, nc = plan.timing_end()
+        ops[name] = {"ms_per_call": round(1000.0 * el / args.steps, 5),
+                     "stages_ms": {n: round(v / max(1, nc), 5) for n, v in zip(snames, sm)}}
+        log(f"{name}: {ops[name]['ms_per_call']:.4f} ms per call")
+    result["operators"] = ops
+
     if args.cpu_baseline == "on":
         log("gpu spectrum for the sample check")
         spec = plan.spectrum(g)

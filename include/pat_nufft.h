@@ -30,7 +30,7 @@
  *
  * Memory and execution model
  *  - All data pointers passed to pat_reconstruct / pat_spectrum /
- *    pat_forward / pat_adjoint are DEVICE pointers on the device that was
+ *    pat_forward / pat_adjoint / pat_forward_dxy are DEVICE pointers on the device that was
  *    current when the plan was created. The plan descriptor's sensor arrays
  *    are HOST pointers; the plan copies them.
  *  - Element type: float for PAT_FP32 and PAT_FP32_KAHAN, double for PAT_FP64.
@@ -158,12 +158,40 @@ pat_status pat_reconstruct(pat_plan* plan, const void* g, void* f, void* workspa
  * F(-K) = conj F(K) gives the rest. */
 pat_status pat_spectrum(pat_plan* plan, const void* g, void* fhat, void* workspace, void* stream);
 
-/* g = A f: the forward model on the Fourier lattice (not yet implemented;
- * returns PAT_ERR_NOT_IMPLEMENTED). */
+/* g = A f: the forward model on the reconstruction's Fourier lattice. The
+ * image f launches the free-space wave of Section 2 (zero initial velocity)
+ * written as a Fourier series with depth period Z:
+ *
+ *   D(K) = dV sum_r f(r) e^{-i K.r},  dV = (X/Nx)(Y/Ny)(Z/Nz),
+ *   g[m][n] = 1/(XYZ) sum_K D(K) e^{i(Kx x_m + Ky y_m)} cos(c|K| t_n),
+ *
+ * K over the lattice minus the planes j = -Nx/2, k = -Ny/2, l = -Nz/2. A
+ * source at depth z also arrives from z - Z; pad the depth so that those
+ * arrivals come after the last sample. Evaluated with the NUFFT steps of the
+ * reconstruction transposed (type-2 interpolation to the sensors), within
+ * the window error of the plan's settings; the sensor areas h_m are not used.
+ * f: DEVICE [Nx][Ny][Nz] real (as pat_reconstruct's output); g: DEVICE [M][Nt]
+ * real, overwritten. Returns PAT_ERR_UNSUPPORTED if the per-column LDS of the
+ * temporal step (Nz/2 * (4 + (2 + width_t) * element size) bytes) exceeds the
+ * device limit. */
 pat_status pat_forward(pat_plan* plan, const void* f, void* g, void* workspace, void* stream);
 
-/* f = A* g: the adjoint of pat_forward (not yet implemented). */
+/* f = A* g: the adjoint of pat_forward for the plain Euclidean inner products
+ * sum_{m,n} g g' and sum_r f f'. It is the reconstruction's pipeline with unit
+ * trace weights (no h_m dt) and the weight W replaced by the constant dV with
+ * e^{-i omega t} averaged over both signs of Kz, i.e. cos(c|K| t), on every
+ * l including l = 0:
+ *   f(r) = 1/(XYZ) sum_K dV sum_n cos(c|K| t_n) sum_m g[m][n] e^{-i(Kx x_m + Ky y_m)} e^{i K.r}.
+ * The device kernels of pat_forward are the exact transposes of these, so
+ * <A f, g> = <f, A* g> holds to rounding. Layouts as pat_reconstruct. */
 pat_status pat_adjoint(pat_plan* plan, const void* g, void* f, void* workspace, void* stream);
+
+/* g = d(A f)/d(x_m) (axis 0) or d(A f)/d(y_m) (axis 1): each trace
+ * differentiated with respect to its own sensor's position, i.e. pat_forward
+ * with i Kx (i Ky) in front of every lattice term. The gradient of a loss
+ * L(A f) with respect to sensor m's x is sum_n dL/dg[m][n] * g[m][n]. Layouts
+ * and errors as pat_forward; PAT_ERR_INVALID_ARGUMENT for another axis. */
+pat_status pat_forward_dxy(pat_plan* plan, const void* f, int32_t axis, void* g, void* workspace, void* stream);
 
 /* Per-stage device timing with HIP events recorded on the call's stream.
  * pat_timing_begin(plan, n) creates events for up to n subsequent compute
@@ -173,7 +201,11 @@ pat_status pat_adjoint(pat_plan* plan, const void* g, void* f, void* workspace, 
  * recorded calls to *calls, and destroys the events. Stages: 0 temporal FFT,
  * 1 lateral spread, 2 lateral FFT along x, 3 lateral FFT along y with
  * deconvolution, 4 temporal interpolation and weight, 5 inverse FFT (the
- * spread and x-FFT run in rounds over bins; their rounds are summed). */
+ * spread and x-FFT run in rounds over bins; their rounds are summed). Calls
+ * of pat_forward and pat_forward_dxy add each kernel's time to the stage it
+ * transposes (5: forward 3-D FFT, 4: transposed interpolation, 3 and 2:
+ * transposed lateral FFTs, 1: interpolation to the sensors, 0: transposed
+ * temporal FFT). */
 #define PAT_TIMING_STAGES 6
 pat_status pat_timing_begin(pat_plan* plan, int32_t max_calls);
 pat_status pat_timing_end(pat_plan* plan, double* ms, int32_t nstage, int32_t* calls);

@@ -102,6 +102,7 @@ struct pat_plan {
   size_t off_C = 0;     // B at off_B (x rows / spectrum), C at off_C (per-sensor bins)
   size_t ws_bytes = 0;
   int64_t spread_pairs = 0;
+  bool forward_ok = false;  // the forward model's per-column LDS fits the device
   // timing: per recorded call, marks_per_call events; mark i > 0 closes the
   // interval of stage ev_stage[i] that began at mark i-1
   std::vector<hipEvent_t> ev;
@@ -200,12 +201,15 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.s_per_k = d.c * d.dt * dp.n_t / (2.0 * M_PI);
   dp.n0_over_nt = double(dp.n0) / double(dp.n_t);
   dp.inv_vol = 1.0 / (d.lx * d.ly * d.lz);
-  // band of oversampled temporal bins read by the interpolation (one bin of margin each side)
+  dp.adj_scale = 0.5 / (double(d.nx) * d.ny * d.nz);
+  // band of oversampled temporal bins read by the interpolation (one bin of
+  // margin each side): |K| from 0 (the l = 0 plane, read by the forward model
+  // and the adjoint) to the largest non-Nyquist lattice point
   {
     const double jx = d.nx / 2 - 1, jy = d.ny / 2 - 1, jz = d.nz / 2 - 1;
     const double Kx = jx * dp.kxu, Ky = jy * dp.kyu, Kz = jz * dp.kzu;
     const double smax = std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz) * dp.s_per_k;
-    const double smin = dp.kzu * dp.s_per_k;
+    const double smin = 0.0;
     const long blo = (long)std::floor(smin) - dp.w_t / 2;
     const long bhi = (long)std::floor(smax) + dp.w_t / 2 + 1;
     if (bhi - blo + 1 > dp.n_t || blo <= -dp.n_t || bhi >= dp.n_t) return PAT_ERR_UNSUPPORTED;
@@ -275,6 +279,17 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   P->spread_pairs = (int64_t)inc.size();
   const size_t o_toff = blob.add(cnt.data(), cnt.size() * sizeof(int));
   const size_t o_tsens = blob.add(sens.data(), std::max<size_t>(1, sens.size()) * sizeof(int));
+  // home lists for the interpolation to the sensors: each sensor once, in
+  // the tile holding its footprint origin, sensors ascending per tile
+  std::vector<int> hcnt(ntiles + 1, 0), home(M);
+  for (int m = 0; m < M; ++m) hcnt[(sby[m] / TS) * dp.tiles_x + sbx[m] / TS + 1]++;
+  for (int i = 0; i < ntiles; ++i) hcnt[i + 1] += hcnt[i];
+  {
+    std::vector<int> pos(hcnt.begin(), hcnt.end() - 1);
+    for (int m = 0; m < M; ++m) home[pos[(sby[m] / TS) * dp.tiles_x + sbx[m] / TS]++] = m;
+  }
+  const size_t o_hoff = blob.add(hcnt.data(), hcnt.size() * sizeof(int));
+  const size_t o_hsens = blob.add(home.data(), home.size() * sizeof(int));
   // lateral deconvolution 1/phihat(j/n), zero on the Nyquist mode j = -N/2
   std::vector<double> dcx(d.nx), dcy(d.ny);
   for (int jj = 0; jj < d.nx; ++jj) {
@@ -324,6 +339,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.swy = at(o_swy);
   dp.tile_off = static_cast<const int*>(at(o_toff));
   dp.tile_sens = static_cast<const int*>(at(o_tsens));
+  dp.home_off = static_cast<const int*>(at(o_hoff));
+  dp.home_sens = static_cast<const int*>(at(o_hsens));
   dp.dcx = at(o_dcx);
   dp.dcy = at(o_dcy);
   dp.hcoef = at(o_hc);
@@ -355,6 +372,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t sz_V = size_t(dp.nb) * d.nx * dp.n_y * c;
   const size_t sz_Gh = size_t(d.nx) * d.ny * dp.nb * c;
   const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
+  P->forward_ok = patk::scatter_lds_bytes<T>(dp) <= (size_t)lds_limit;
   const size_t szA = align_up(std::max(sz_U, sz_Gh));
   const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;
@@ -399,8 +417,12 @@ struct Marker {
 
 inline int rounds(const patk::DevPlan& dp) { return (dp.nb + dp.chunk_bins - 1) / dp.chunk_bins; }
 
+enum Op { OP_RECONSTRUCT, OP_SPECTRUM, OP_ADJOINT, OP_FORWARD, OP_FORWARD_DX, OP_FORWARD_DY };
+
+// Reconstruction, physical spectrum and adjoint: traces in, image (or
+// spectrum) out. The adjoint uses unit trace weights and the adjoint gather.
 template <typename T>
-pat_status run(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, bool spectrum_only) {
+pat_status run_traces_in(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, Op op) {
   const patk::DevPlan& dp = P->dp;
   unsigned char* A = static_cast<unsigned char*>(ws);
   unsigned char* B = A + P->off_B;
@@ -408,7 +430,8 @@ pat_status run(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, b
   Marker mark{P, P->ev_used < P->ev_max ? P->ev_used++ : -1, 0, s};
   hipError_t e;
   mark(-1);
-  if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), C, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), C, op != OP_ADJOINT, s)) != hipSuccess)
+    return to_status(e);
   mark(0);
   for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
     const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
@@ -419,15 +442,47 @@ pat_status run(pat_plan* P, const void* g, void* out, void* ws, hipStream_t s, b
   }
   if ((e = patk::launch_fft_y<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
   mark(3);
-  if (spectrum_only) {
-    if ((e = patk::launch_gather<T>(dp, A, out, true, s)) != hipSuccess) return to_status(e);
+  if (op == OP_SPECTRUM) {
+    if ((e = patk::launch_gather<T>(dp, A, out, patk::GATHER_PHYSICAL, s)) != hipSuccess) return to_status(e);
     mark(4);
     return PAT_OK;
   }
-  if ((e = patk::launch_gather<T>(dp, A, B, false, s)) != hipSuccess) return to_status(e);
+  const int mode = op == OP_ADJOINT ? patk::GATHER_ADJOINT : patk::GATHER_IMAGE;
+  if ((e = patk::launch_gather<T>(dp, A, B, mode, s)) != hipSuccess) return to_status(e);
   mark(4);
   if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s)) != hipSuccess) return to_status(e);
   mark(5);
+  return PAT_OK;
+}
+
+// Forward model (and its position derivatives): image in, traces out; the
+// transposes of the adjoint's stages in reverse order. Timing marks use the
+// stage index of the stage each kernel transposes.
+template <typename T>
+pat_status run_image_in(pat_plan* P, const void* f, void* g, void* ws, hipStream_t s, Op op) {
+  const patk::DevPlan& dp = P->dp;
+  unsigned char* A = static_cast<unsigned char*>(ws);
+  unsigned char* B = A + P->off_B;
+  unsigned char* C = A + P->off_C;
+  Marker mark{P, P->ev_used < P->ev_max ? P->ev_used++ : -1, 0, s};
+  hipError_t e;
+  const int deriv = op == OP_FORWARD_DX ? 1 : (op == OP_FORWARD_DY ? 2 : 0);
+  mark(-1);
+  if ((e = patk::launch_forward3d<T>(dp, static_cast<const T*>(f), B, s)) != hipSuccess) return to_status(e);
+  mark(5);
+  if ((e = patk::launch_scatter<T>(dp, B, A, deriv, s)) != hipSuccess) return to_status(e);
+  mark(4);
+  if ((e = patk::launch_fft_y_t<T>(dp, A, B, s)) != hipSuccess) return to_status(e);
+  mark(3);
+  for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
+    const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
+    if ((e = patk::launch_fft_x_t<T>(dp, B, A, b0, b1, s)) != hipSuccess) return to_status(e);
+    mark(2);
+    if ((e = patk::launch_interp<T>(dp, A, C, b0, b1, s)) != hipSuccess) return to_status(e);
+    mark(1);
+  }
+  if ((e = patk::launch_temporal_t<T>(dp, C, static_cast<T*>(g), s)) != hipSuccess) return to_status(e);
+  mark(0);
   return PAT_OK;
 }
 
@@ -437,20 +492,26 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-pat_status compute(pat_plan* P, const void* g, void* out, void* ws, void* stream, bool spectrum_only) {
-  if (!P || !g || !out || !ws) return PAT_ERR_INVALID_ARGUMENT;
+pat_status compute(pat_plan* P, const void* in, void* out, void* ws, void* stream, Op op) {
+  if (!P || !in || !out || !ws) return PAT_ERR_INVALID_ARGUMENT;
   if ((reinterpret_cast<uintptr_t>(ws) % kAlign) != 0) return PAT_ERR_INVALID_ARGUMENT;
   const size_t eb = P->fp64 ? 8 : 4;
-  const size_t g_bytes = size_t(P->d.n_sensors) * P->d.n_t * eb;
-  const size_t o_bytes = spectrum_only ? size_t(P->d.nx) * P->d.ny * (P->d.nz / 2 + 1) * 2 * eb
-                                       : size_t(P->d.nx) * P->d.ny * P->d.nz * eb;
-  if (overlaps(g, g_bytes, out, o_bytes) || overlaps(g, g_bytes, ws, P->ws_bytes) ||
+  const size_t traces = size_t(P->d.n_sensors) * P->d.n_t * eb;
+  const size_t image = size_t(P->d.nx) * P->d.ny * P->d.nz * eb;
+  const size_t half = size_t(P->d.nx) * P->d.ny * (P->d.nz / 2 + 1) * 2 * eb;
+  const bool image_in = op == OP_FORWARD || op == OP_FORWARD_DX || op == OP_FORWARD_DY;
+  const size_t i_bytes = image_in ? image : traces;
+  const size_t o_bytes = image_in ? traces : (op == OP_SPECTRUM ? half : image);
+  if (overlaps(in, i_bytes, out, o_bytes) || overlaps(in, i_bytes, ws, P->ws_bytes) ||
       overlaps(out, o_bytes, ws, P->ws_bytes))
     return PAT_ERR_INVALID_ARGUMENT;
+  if (image_in && !P->forward_ok) return PAT_ERR_UNSUPPORTED;
   DeviceGuard guard(P->device);
   if (!guard.ok) return PAT_ERR_HIP;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  return P->fp64 ? run<double>(P, g, out, ws, s, spectrum_only) : run<float>(P, g, out, ws, s, spectrum_only);
+  if (image_in)
+    return P->fp64 ? run_image_in<double>(P, in, out, ws, s, op) : run_image_in<float>(P, in, out, ws, s, op);
+  return P->fp64 ? run_traces_in<double>(P, in, out, ws, s, op) : run_traces_in<float>(P, in, out, ws, s, op);
 }
 
 void destroy_events(pat_plan* P) {
@@ -540,27 +601,24 @@ pat_status nufft_plan_destroy(pat_plan* P) {
 }
 
 pat_status pat_reconstruct(pat_plan* P, const void* g, void* f, void* ws, void* stream) {
-  return compute(P, g, f, ws, stream, false);
+  return compute(P, g, f, ws, stream, OP_RECONSTRUCT);
 }
 
 pat_status pat_spectrum(pat_plan* P, const void* g, void* fhat, void* ws, void* stream) {
-  return compute(P, g, fhat, ws, stream, true);
+  return compute(P, g, fhat, ws, stream, OP_SPECTRUM);
 }
 
 pat_status pat_forward(pat_plan* P, const void* f, void* g, void* ws, void* stream) {
-  (void)f;
-  (void)g;
-  (void)ws;
-  (void)stream;
-  return P ? PAT_ERR_NOT_IMPLEMENTED : PAT_ERR_INVALID_ARGUMENT;
+  return compute(P, f, g, ws, stream, OP_FORWARD);
 }
 
 pat_status pat_adjoint(pat_plan* P, const void* g, void* f, void* ws, void* stream) {
-  (void)f;
-  (void)g;
-  (void)ws;
-  (void)stream;
-  return P ? PAT_ERR_NOT_IMPLEMENTED : PAT_ERR_INVALID_ARGUMENT;
+  return compute(P, g, f, ws, stream, OP_ADJOINT);
+}
+
+pat_status pat_forward_dxy(pat_plan* P, const void* f, int32_t axis, void* g, void* ws, void* stream) {
+  if (axis != 0 && axis != 1) return PAT_ERR_INVALID_ARGUMENT;
+  return compute(P, f, g, ws, stream, axis == 0 ? OP_FORWARD_DX : OP_FORWARD_DY);
 }
 
 pat_status pat_timing_begin(pat_plan* P, int32_t max_calls) {

@@ -1,5 +1,6 @@
 // Temporal interpolation at omega(K) with the inversion weight
-// (Section 3.1, eq. NER_NUFFT; Section 2, eq. exact).
+// (Section 3.1, eq. NER_NUFFT; Section 2, eq. exact), the adjoint's
+// cos(c|K|t) form of it, and the exact transpose used by the forward model.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -8,19 +9,60 @@
 
 namespace patk {
 
-// ---------------------------------------------------------------------------
-// Stage 4: temporal interpolation at omega(K) (the window sum of
-// eq. NER_NUFFT with the centring phase of eq. PSI) and the inversion
-// weight of eq. exact. For lateral mode (j,k) and l = 1..Nz/2-1:
-//   s  = c |K| dt n_t / (2 pi)                  (double)
-//   S  = exp(-2 pi i s n0/n_t) sum_t phi_t(s - b_t) Gh[j][k][b_t]
-//   F  = 2c Kz/|K| * S
-// The l = 0, l = Nz/2, j = -Nx/2 and k = -Ny/2 entries are written as 0.
-// ---------------------------------------------------------------------------
+// Interpolation point of lattice mode (j, k, l >= 0): s = c|K| dt n_t/(2 pi)
+// in oversampled bins (double), the first band bin of its w_t taps (clamped
+// to the band), the tap argument y = 2 frac(s) - 1 and the centring phase
+// exp(-2 pi i s n0/n_t) of eq. PSI (samples sit at n - n0 in the FFT).
+struct TapPoint {
+  int base;
+  double y;
+  double cs, sn;
+};
+
+__device__ __forceinline__ TapPoint tap_point(double Kabs, double s_per_k, double n0_over_nt, int wt, int b_lo,
+                                              int nb) {
+  TapPoint tp;
+  const double s = Kabs * s_per_k;
+  const double fl = floor(s);
+  tp.y = 2.0 * (s - fl) - 1.0;
+  int base = int(fl) - wt / 2 + 1 - b_lo;
+  tp.base = base < 0 ? 0 : (base > nb - wt ? nb - wt : base);
+  double q = s * n0_over_nt;
+  q -= floor(q);
+  sincos(-2.0 * M_PI * q, &tp.sn, &tp.cs);
+  return tp;
+}
+
+// Tap weight t of the temporal window at argument y (Horner on the per-tap
+// polynomial fitted at plan time).
 template <typename T>
+__device__ __forceinline__ T tap_weight(const T* __restrict__ hcoef, int t, int deg, T y) {
+  const T* c = hcoef + t * (deg + 1);
+  T v = c[deg];
+  for (int d = deg - 1; d >= 0; --d) v = v * y + c[d];
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Stage 4: temporal interpolation, one thread per (j, k, l), l = 0..Nz/2.
+//   S+(K) = exp(-2 pi i s n0/n_t) sum_t phi_t(s - b_t) Gh[j][k][b_t]
+// MODE_IMAGE / MODE_PHYSICAL (reconstruction, eq. exact):
+//   F = 2c Kz/|K| * S+ on l = 1..Nz/2-1; 0 on l = 0, l = Nz/2 and the
+//   j = -Nx/2, k = -Ny/2 planes. MODE_IMAGE scales by 1/(XYZ) for the
+//   inverse transform; MODE_PHYSICAL restores the (-1)^(j+k) sign of the
+//   centred lateral coordinates instead.
+// MODE_ADJOINT (adjoint of the forward model): the time kernel is
+//   cos(c|K|t) = (e^{-i c|K| t} + e^{+i c|K| t})/2, and the second term is
+//   the conjugate of S+ at (-Kx, -Ky) because the data are real, so
+//   F = scale * (S+(j,k,l) + conj S+(-j,-k,l)) on l = 0..Nz/2-1 (l = 0
+//   included), 0 on l = Nz/2 and the two lateral Nyquist planes.
+// ---------------------------------------------------------------------------
+enum { MODE_IMAGE = 0, MODE_PHYSICAL = 1, MODE_ADJOINT = 2 };
+
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
                                                 double s_per_k, double kxu, double kyu, double kzu, double two_c,
-                                                double n0_over_nt, double scale, int physical, int wt, int deg,
+                                                double n0_over_nt, double scale, int wt, int deg,
                                                 const T* __restrict__ hcoef, cx<T>* __restrict__ Fh) {
   const int Lh = Nz / 2 + 1;
   const long long total = (long long)Nx * Ny * Lh;
@@ -30,7 +72,8 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, in
   const long long col = idx / Lh;
   const int kk = int(col % Ny);
   const int jj = int(col / Ny);
-  if (l == 0 || l == Nz / 2 || jj == Nx / 2 || kk == Ny / 2) {
+  const bool zero_l = MODE == MODE_ADJOINT ? (l == Nz / 2) : (l == 0 || l == Nz / 2);
+  if (zero_l || jj == Nx / 2 || kk == Ny / 2) {
     Fh[idx] = cx<T>{T(0), T(0)};
     return;
   }
@@ -38,44 +81,173 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, in
   const int k = kk < Ny / 2 ? kk : kk - Ny;
   const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
   const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
-  const double s = Kabs * s_per_k;
-  const double fl = floor(s);
-  const T y = T(2.0 * (s - fl) - 1.0);
-  int base = int(fl) - wt / 2 + 1 - b_lo;
-  base = base < 0 ? 0 : (base > nb - wt ? nb - wt : base);
-  const cx<T>* src = Gh + col * nb + base;
-  cx<T> acc{T(0), T(0)};
-  const int np = deg + 1;
+  const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
+  const T y = T(tp.y);
+  const cx<T>* src = Gh + col * nb + tp.base;
+  const cx<T>* src2 = Gh + ((long long)((Nx - jj) % Nx) * Ny + (Ny - kk) % Ny) * nb + tp.base;
+  cx<T> acc{T(0), T(0)}, acc2{T(0), T(0)};
   for (int t = 0; t < wt; ++t) {
-    const T* c = hcoef + t * np;
-    T v = c[deg];
-    for (int d = deg - 1; d >= 0; --d) v = v * y + c[d];
+    const T v = tap_weight(hcoef, t, deg, y);
     const cx<T> gv = src[t];
     acc.x += v * gv.x;
     acc.y += v * gv.y;
+    if (MODE == MODE_ADJOINT) {
+      const cx<T> gv2 = src2[t];
+      acc2.x += v * gv2.x;
+      acc2.y += v * gv2.y;
+    }
   }
-  double q = s * n0_over_nt;
-  q -= floor(q);
-  double sn, cs;
-  sincos(-2.0 * M_PI * q, &sn, &cs);
+  if (MODE == MODE_ADJOINT) {
+    const cx<T> ph{T(tp.cs * scale), T(tp.sn * scale)};
+    const cx<T> a = cmul(acc, ph), b = cmul(acc2, ph);
+    Fh[idx] = cx<T>{a.x + b.x, a.y - b.y};
+    return;
+  }
   double wgt = two_c * Kz / Kabs * scale;
-  if (physical && ((jj + kk) & 1)) wgt = -wgt;
-  const cx<T> ph{T(wgt * cs), T(wgt * sn)};
+  if (MODE == MODE_PHYSICAL && ((jj + kk) & 1)) wgt = -wgt;
+  const cx<T> ph{T(wgt * tp.cs), T(wgt * tp.sn)};
   Fh[idx] = cmul(acc, ph);
 }
 
 template <typename T>
-hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, bool physical, hipStream_t s) {
+hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, int mode, hipStream_t s) {
   const long long total = (long long)p.Nx * p.Ny * (p.Nz / 2 + 1);
   const unsigned blocks = (unsigned)((total + 255) / 256);
-  const double scale = physical ? 1.0 : p.inv_vol;
-  hipLaunchKernelGGL(k_gather<T>, dim3(blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gh), p.nb, p.b_lo, p.Nx,
-                     p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, scale, physical ? 1 : 0,
-                     p.w_t, p.hdeg, static_cast<const T*>(p.hcoef), static_cast<cx<T>*>(Fh));
+  const cx<T>* in = static_cast<const cx<T>*>(Gh);
+  cx<T>* out = static_cast<cx<T>*>(Fh);
+  const T* hc = static_cast<const T*>(p.hcoef);
+  switch (mode) {
+    case GATHER_IMAGE:
+      hipLaunchKernelGGL((k_gather<T, MODE_IMAGE>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
+                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.inv_vol, p.w_t, p.hdeg, hc,
+                         out);
+      break;
+    case GATHER_PHYSICAL:
+      hipLaunchKernelGGL((k_gather<T, MODE_PHYSICAL>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
+                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, 1.0, p.w_t, p.hdeg, hc, out);
+      break;
+    case GATHER_ADJOINT:
+      hipLaunchKernelGGL((k_gather<T, MODE_ADJOINT>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
+                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.adj_scale, p.w_t, p.hdeg,
+                         hc, out);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-#define PATK_INST(T) template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, bool, hipStream_t);
+// ---------------------------------------------------------------------------
+// Transpose of MODE_ADJOINT (the forward model's temporal step). Input: the
+// forward-transformed image Dh[j][k][l], l = 0..Nz/2 (real-input transform
+// along z, so Dh(-j,-k,l) pairs with Dh(j,k,-l)). One work-group owns the
+// lateral column (j, k) and writes its band Gh'[j][k][0..nb):
+//   Gh'[b] = sum_l phi_{b - base_l}(y_l) Z_l,
+//   Z_l = scale c_l conj(phase_l) m(j,k) (Dh(j,k,l) + conj Dh(-j,-k,l)),
+// over l = 0..Nz/2-1, with c_l = 1 at l = 0 and 2 otherwise (the two
+// z-halves of the real-to-complex transform) and m = 1, i Kx or i Ky (the
+// derivative of the traces in the sensor's x or y); Z = 0 on the Nyquist
+// columns. Interpolation points and tap weights are computed exactly as in
+// k_gather. Every bin sums its contributions in increasing l (the taps'
+// first bins are non-decreasing in l), so the result is deterministic and
+// atomic-free. A work-group handles a few consecutive columns so that the
+// per-l phase keeps its threads busy.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                                 double s_per_k, double kxu, double kyu, double kzu, double n0_over_nt,
+                                                 double scale, int deriv, int wt, int deg, const T* __restrict__ hcoef,
+                                                 int cols_per_group, cx<T>* __restrict__ Gh) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int Lz = Nz / 2;
+  const int Lh = Lz + 1;
+  const int ncol_total = Nx * Ny;
+  const int col0 = blockIdx.x * cols_per_group;
+  const int ncol = min(cols_per_group, ncol_total - col0);
+  cx<T>* s_z = reinterpret_cast<cx<T>*>(smem_raw);                  // [ncol][Lz]
+  T* s_w = reinterpret_cast<T*>(s_z + cols_per_group * Lz);          // [ncol][Lz][wt]
+  int* s_base = reinterpret_cast<int*>(s_w + cols_per_group * Lz * wt);  // [ncol][Lz]
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  for (int q = tid; q < ncol * Lz; q += nthr) {
+    const int ci = q / Lz;
+    const int l = q - ci * Lz;
+    const int col = col0 + ci;
+    const int jj = col / Ny, kk = col - (col / Ny) * Ny;
+    const int j = jj < Nx / 2 ? jj : jj - Nx;
+    const int k = kk < Ny / 2 ? kk : kk - Ny;
+    const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
+    const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+    const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
+    const T y = T(tp.y);
+    for (int t = 0; t < wt; ++t) s_w[q * wt + t] = tap_weight(hcoef, t, deg, y);
+    s_base[q] = tp.base;
+    cx<T> z{T(0), T(0)};
+    if (jj != Nx / 2 && kk != Ny / 2) {
+      const cx<T> a = Dh[(size_t)col * Lh + l];
+      const cx<T> b = Dh[((size_t)((Nx - jj) % Nx) * Ny + (Ny - kk) % Ny) * Lh + l];
+      cx<T> u{a.x + b.x, a.y - b.y};
+      if (deriv == 1) u = cx<T>{T(-Kx) * u.y, T(Kx) * u.x};
+      if (deriv == 2) u = cx<T>{T(-Ky) * u.y, T(Ky) * u.x};
+      const double sc = (l == 0 ? 1.0 : 2.0) * scale;
+      z = cmul(u, cx<T>{T(tp.cs * sc), T(-tp.sn * sc)});
+    }
+    s_z[q] = z;
+  }
+  __syncthreads();
+  for (int q = tid; q < ncol * nb; q += nthr) {
+    const int ci = q / nb;
+    const int b = q - ci * nb;
+    const int* base = s_base + ci * Lz;
+    // contributions come from the l with base_l in [b - wt + 1, b]
+    int lo = 0, hi = Lz;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (base[mid] < b - wt + 1) lo = mid + 1; else hi = mid;
+    }
+    cx<T> acc{T(0), T(0)};
+    for (int l = lo; l < Lz && base[l] <= b; ++l) {
+      const T v = s_w[(ci * Lz + l) * wt + (b - base[l])];
+      const cx<T> z = s_z[ci * Lz + l];
+      acc.x += v * z.x;
+      acc.y += v * z.y;
+    }
+    Gh[(size_t)(col0 + ci) * nb + b] = acc;
+  }
+}
+
+// lateral columns per work-group: enough (l) rows to occupy 256 threads
+template <typename T>
+static int scatter_cols(const DevPlan& p) {
+  const int Lz = p.Nz / 2;
+  int c = 256 / Lz;
+  return c < 1 ? 1 : (c > 8 ? 8 : c);
+}
+
+template <typename T>
+size_t scatter_lds_bytes(const DevPlan& p) {
+  const size_t Lz = size_t(p.Nz / 2) * scatter_cols<T>(p);
+  return Lz * sizeof(cx<T>) + Lz * p.w_t * sizeof(T) + Lz * sizeof(int);
+}
+
+template <typename T>
+hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv, hipStream_t s) {
+  if (deriv < 0 || deriv > 2) return hipErrorInvalidValue;
+  const size_t lds = scatter_lds_bytes<T>(p);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_scatter<T>), lds);
+  if (e != hipSuccess) return e;
+  const int cpg = scatter_cols<T>(p);
+  const int ncol = p.Nx * p.Ny;
+  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((ncol + cpg - 1) / cpg)), dim3(256), lds, s,
+                     static_cast<const cx<T>*>(Dh), p.nb, p.b_lo, p.Nx, p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu,
+                     p.n0_over_nt, p.adj_scale, deriv, p.w_t, p.hdeg, static_cast<const T*>(p.hcoef), cpg,
+                     static_cast<cx<T>*>(Gh));
+  return hipGetLastError();
+}
+
+#define PATK_INST(T)                                                                     \
+  template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
+  template size_t scatter_lds_bytes<T>(const DevPlan&);                                  \
+  template hipError_t launch_scatter<T>(const DevPlan&, const void*, void*, int, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -1,5 +1,5 @@
 // Equispaced inverse 3-D FFT of the weighted spectrum (the last step of the
-// NEDNER list in Section 3).
+// NEDNER list in Section 3), and its transpose for the forward model.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -13,8 +13,8 @@ namespace patk {
 // half spectrum Fh[jj][kk][l], l = 0..Nz/2: in-place inverse transforms
 // along x and along y, then a complex-to-real transform along z.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
+template <typename T, bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
                                                       FftDesc<T> fd, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
   __syncthreads();
-  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
@@ -50,8 +50,8 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_x(cx<T>* __restrict__ F, i
       });
 }
 
-template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm) {
+template <typename T, bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kFftThreads) void k_ifft_y(cx<T>* __restrict__ F, i
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
   __syncthreads();
-  fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
@@ -119,44 +119,99 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
       [&](int q, T v) { f[r0 * Nz + q] = v; });
 }
 
+// Transpose of k_c2r_z for the forward model: real rows f[r][e] ->
+// Dh[r][l] = sum_e f[r][e] exp(-2 pi i l e/Nz), l = 0..Nz/2.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, long long nrows, int rows,
+                                                     FftDesc<T> fd, cx<T>* __restrict__ D) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Nz = fd.n;
+  const int Lh = Nz / 2 + 1;
+  const int bstride = lseq(Nz);
+  const long long r0 = (long long)blockIdx.x * rows;
+  const int nr = (int)min((long long)rows, nrows - r0);
+  const FastDiv div_lh(Lh), div_nz(Nz);
+  staged_copy<kFftMaxV>(
+      nr * Nz, tid, nthr, [&](int q) { return f[r0 * Nz + q]; },
+      [&](int q, T v) {
+        const int r = div_nz(q);
+        buf[r * bstride + lpos(q - r * Nz)] = cx<T>{v, T(0)};
+      });
+  __syncthreads();
+  fft_lds<T, kFftMaxV, false, false>(buf, fd, nr, bstride, tid, nthr);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nr * Lh, tid, nthr,
+      [&](int q) {
+        const int r = div_lh(q);
+        return buf[r * bstride + lpos(q - r * Lh)];
+      },
+      [&](int q, cx<T> v) { D[r0 * Lh + q] = v; });
+}
+
+// In-place transforms of the half spectrum along x and y (INV: e^{+i}).
+template <typename T, bool INV>
+static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_t s) {
+  const int Lh = p.Nz / 2 + 1;
+  const FftCfg cfg = fft_cfg();
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool along_x = (pass == 0) == x_first;
+    hipError_t e;
+    if (along_x) {
+      const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
+      const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
+      if ((e = allow_lds(reinterpret_cast<const void*>(&k_cfft_x<T, INV>), lds)) != hipSuccess) return e;
+      dim3 grid((Lh + lc - 1) / lc, p.Ny);
+      hipLaunchKernelGGL((k_cfft_x<T, INV>), grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx),
+                         cfg.wave);
+    } else {
+      const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
+      const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
+      if ((e = allow_lds(reinterpret_cast<const void*>(&k_cfft_y<T, INV>), lds)) != hipSuccess) return e;
+      dim3 grid((Lh + lc - 1) / lc, p.Nx);
+      hipLaunchKernelGGL((k_cfft_y<T, INV>), grid, dim3(cfg.threads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny),
+                         cfg.wave);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   cx<T>* F = static_cast<cx<T>*>(Fh);
-  const int Lh = p.Nz / 2 + 1;
+  hipError_t e = launch_xy<T, true>(p, F, true, s);
+  if (e != hipSuccess) return e;
   const FftCfg cfg = fft_cfg();
-  {
-    const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
-    const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_x<T>), lds);
-    if (e != hipSuccess) return e;
-    dim3 grid((Lh + lc - 1) / lc, p.Ny);
-    hipLaunchKernelGGL(k_ifft_x<T>, grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx), cfg.wave);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  {
-    const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
-    const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_ifft_y<T>), lds);
-    if (e != hipSuccess) return e;
-    dim3 grid((Lh + lc - 1) / lc, p.Nx);
-    hipLaunchKernelGGL(k_ifft_y<T>, grid, dim3(cfg.threads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny), cfg.wave);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  {
-    const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
-    const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds);
-    if (e != hipSuccess) return e;
-    const long long nrows = (long long)p.Nx * p.Ny;
-    hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, F, nrows,
-                       rows, as_desc<T>(p.f_Nz), f, cfg.wave);
-  }
+  const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
+  const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+  if ((e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds)) != hipSuccess) return e;
+  const long long nrows = (long long)p.Nx * p.Ny;
+  hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, F, nrows,
+                     rows, as_desc<T>(p.f_Nz), f, cfg.wave);
   return hipGetLastError();
 }
 
-#define PATK_INST(T) template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t);
+template <typename T>
+hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t s) {
+  cx<T>* D = static_cast<cx<T>*>(Dh);
+  const FftCfg cfg = fft_cfg();
+  const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
+  const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_r2c_z<T>), lds);
+  if (e != hipSuccess) return e;
+  const long long nrows = (long long)p.Nx * p.Ny;
+  hipLaunchKernelGGL(k_r2c_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, f, nrows,
+                     rows, as_desc<T>(p.f_Nz), D);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_xy<T, false>(p, D, false, s);
+}
+
+#define PATK_INST(T)                                                                \
+  template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t); \
+  template hipError_t launch_forward3d<T>(const DevPlan&, const T*, void*, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

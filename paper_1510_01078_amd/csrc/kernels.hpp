@@ -43,6 +43,7 @@ struct DevPlan {
   double two_c = 0.0;          // 2c of W(K) = 2c|Kz|/|K|
   double n0_over_nt = 0.0;     // centring phase factor n0/n_t
   double inv_vol = 0.0;        // 1/(XYZ)
+  double adj_scale = 0.0;      // dV/(2V) = 1/(2 Nx Ny Nz): the adjoint's constant weight with the 1/V of the inverse
   // device tables (element type T unless int)
   const void* hw = nullptr;       // [M]   h_m*dt
   const void* deap = nullptr;     // [Nt]  1/phihat_t((n - n0)/n_t)
@@ -52,6 +53,8 @@ struct DevPlan {
   const void* swy = nullptr;      // [M][w]
   const int* tile_off = nullptr;  // [tiles+1]
   const int* tile_sens = nullptr; // sensors whose footprint meets each tile
+  const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
+  const int* home_sens = nullptr; // [M]
   const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
   const void* dcy = nullptr;      // [Ny]
   const void* hcoef = nullptr;    // [w_t][hdeg+1] temporal tap polynomials
@@ -61,8 +64,16 @@ struct DevPlan {
 constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
 
 // Stage launchers; T = float or double. Buffers are device pointers.
+//
+// Reconstruction and adjoint: temporal -> spread -> fft_x -> fft_y -> gather
+// -> inverse. Forward model (the exact transpose of the adjoint's stages, in
+// reverse order): forward3d -> scatter -> fft_y_t -> fft_x_t -> interp ->
+// temporal_t.
+
+// weighted = true: traces scaled by h_m dt (reconstruction); false: unit
+// weights (adjoint of the forward model).
 template <typename T>
-hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s);
+hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted, hipStream_t s);
 // Bins [b_begin, b_end) of the band: U holds only those bins (U[b - b_begin]),
 // V all bins.
 template <typename T>
@@ -71,11 +82,34 @@ template <typename T>
 hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s);
 template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s);
-// physical = true: F(K) as defined (sign (-1)^(j+k), no 1/V); false: the
-// image-ready spectrum (-1)^(j+k) F(K) / (XYZ) consumed by launch_inverse.
+// GATHER_PHYSICAL: F(K) as defined (sign (-1)^(j+k), no 1/V); GATHER_IMAGE:
+// the image-ready spectrum (-1)^(j+k) F(K) / (XYZ) consumed by
+// launch_inverse; GATHER_ADJOINT: the adjoint's image-ready spectrum.
+enum { GATHER_IMAGE = 0, GATHER_PHYSICAL = 1, GATHER_ADJOINT = 2 };
 template <typename T>
-hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, bool physical, hipStream_t s);
+hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, int mode, hipStream_t s);
 template <typename T>
 hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s);
+
+// Forward model. f -> Dh (real-to-complex along z, forward FFTs along y, x)
+template <typename T>
+hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t s);
+// Dh -> Gh' (deriv 0: A; 1: d/dx_m; 2: d/dy_m); LDS bytes it needs
+template <typename T>
+hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv, hipStream_t s);
+template <typename T>
+size_t scatter_lds_bytes(const DevPlan& p);
+// Gh'[j][k][b] -> V'[b][j][py]
+template <typename T>
+hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t s);
+// V'[b][j][py] -> U'[b - b_begin][py][px] for bins [b_begin, b_end)
+template <typename T>
+hipError_t launch_fft_x_t(const DevPlan& p, const void* V, void* U, int b_begin, int b_end, hipStream_t s);
+// U' (bins [b_begin, b_end)) -> Gt'[m][b] at the sensors
+template <typename T>
+hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin, int b_end, hipStream_t s);
+// Gt' -> g[m][n] (unit weights)
+template <typename T>
+hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s);
 
 }  // namespace patk

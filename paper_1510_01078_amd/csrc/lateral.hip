@@ -130,9 +130,141 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Transposes for the forward model (conjugate transposes of k_fft_y and
+// k_fft_x: embed the cropped modes into the oversampled length with zeros,
+// inverse FFT).
+// Gh'[j][k][b] -> V'[b][j][py] = dcx_j sum_k dcy_k Gh'[j][k][b] e^{+2 pi i k py/n_y}
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict__ Gh, int nb, int Nx, int Ny,
+                                                       int bins, const T* __restrict__ dcx,
+                                                       const T* __restrict__ dcy, FftDesc<T> fd,
+                                                       cx<T>* __restrict__ V) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_y = fd.n;
+  const int bstride = lseq(n_y);
+  const int jj = blockIdx.y;
+  const int b0 = blockIdx.x * bins;
+  const int nbc = min(bins, nb - b0);
+  const int gap = n_y - Ny;  // zero slots k = Ny/2 .. n_y - Ny/2 - 1
+  const FastDiv div_gap(gap), div_nbc(nbc), div_ny(n_y);
+  for (int q = tid; q < nbc * gap; q += nthr) {
+    const int bi = div_gap(q);
+    buf[bi * bstride + lpos(Ny / 2 + (q - bi * gap))] = cx<T>{T(0), T(0)};
+  }
+  const T cxj = dcx[jj];
+  const cx<T>* src = Gh + size_t(jj) * Ny * nb + b0;
+  staged_copy<kFftMaxV>(
+      nbc * Ny, tid, nthr,
+      [&](int q) {
+        const int kk = div_nbc(q);
+        const T sc = cxj * dcy[kk];
+        const cx<T> v = src[size_t(kk) * nb + (q - kk * nbc)];
+        return cx<T>{v.x * sc, v.y * sc};
+      },
+      [&](int q, cx<T> v) {
+        const int kk = div_nbc(q);
+        const int k = kk < Ny / 2 ? kk : kk - Ny;
+        buf[(q - kk * nbc) * bstride + lpos(k < 0 ? k + n_y : k)] = v;
+      });
+  __syncthreads();
+  fft_lds<T, kFftMaxV, true, false>(buf, fd, nbc, bstride, tid, nthr);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nbc * n_y, tid, nthr,
+      [&](int q) {
+        const int bi = div_ny(q);
+        return buf[bi * bstride + lpos(q - bi * n_y)];
+      },
+      [&](int q, cx<T> v) {
+        const int bi = div_ny(q);
+        V[(size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y)] = v;
+      });
+}
+
+template <typename T>
+hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t s) {
+  const FftCfg cfg = fft_cfg();
+  const int bins = fft_batch<T>(p.n_y, cfg.threads, cfg.cap);
+  const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
+    return hipErrorInvalidValue;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y_t<T>), lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+  hipLaunchKernelGGL(k_fft_y_t<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(Gh), p.nb, p.Nx, p.Ny,
+                     bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
+                     static_cast<cx<T>*>(V));
+  return hipGetLastError();
+}
+
+// V'[b][j][py] -> U'[b - b_begin][py][px] = sum_j V'[b][j][py] e^{+2 pi i j px/n_x}
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_t(const cx<T>* __restrict__ V, int n_y, int Nx, int rows,
+                                                       int b_begin, FftDesc<T> fd, cx<T>* __restrict__ U) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_x = fd.n;
+  const int bstride = lseq(n_x);
+  const int b = b_begin + blockIdx.y;
+  const int py0 = blockIdx.x * rows;
+  const int nr = min(rows, n_y - py0);
+  const int gap = n_x - Nx;
+  const FastDiv div_gap(gap), div_nr(nr), div_nx(n_x);
+  for (int q = tid; q < nr * gap; q += nthr) {
+    const int r = div_gap(q);
+    buf[r * bstride + lpos(Nx / 2 + (q - r * gap))] = cx<T>{T(0), T(0)};
+  }
+  const cx<T>* src = V + size_t(b) * Nx * n_y + py0;
+  staged_copy<kFftMaxV>(
+      nr * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nr(q);
+        return src[size_t(jj) * n_y + (q - jj * nr)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nr(q);
+        const int j = jj < Nx / 2 ? jj : jj - Nx;
+        buf[(q - jj * nr) * bstride + lpos(j < 0 ? j + n_x : j)] = v;
+      });
+  __syncthreads();
+  fft_lds<T, kFftMaxV, true, false>(buf, fd, nr, bstride, tid, nthr);
+  __syncthreads();
+  cx<T>* dst = U + (size_t(b - b_begin) * n_y + py0) * n_x;
+  staged_copy<kFftMaxV>(
+      nr * n_x, tid, nthr,
+      [&](int q) {
+        const int r = div_nx(q);
+        return buf[r * bstride + lpos(q - r * n_x)];
+      },
+      [&](int q, cx<T> v) { dst[q] = v; });
+}
+
+template <typename T>
+hipError_t launch_fft_x_t(const DevPlan& p, const void* V, void* U, int b_begin, int b_end, hipStream_t s) {
+  const FftCfg cfg = fft_cfg();
+  const int rows = fft_batch<T>(p.n_x, cfg.threads, cfg.cap);
+  const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
+  if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
+      b_begin < 0 || b_end > p.nb || b_begin >= b_end)
+    return hipErrorInvalidValue;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_t<T>), lds);
+  if (e != hipSuccess) return e;
+  dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
+  hipLaunchKernelGGL(k_fft_x_t<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.n_y, p.Nx, rows,
+                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(U));
+  return hipGetLastError();
+}
+
 #define PATK_INST(T)                                                                    \
   template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
-  template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);
+  template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);          \
+  template hipError_t launch_fft_y_t<T>(const DevPlan&, const void*, void*, hipStream_t);        \
+  template hipError_t launch_fft_x_t<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -12,7 +12,8 @@ namespace patk {
 // Stage 0: temporal FFT per sensor (the equispaced half of eq. NER_NUFFT).
 // Two real traces share one complex FFT (re = sensor m0, im = sensor m1).
 // Sample n sits at index (n - n0) mod n_t after multiplication by
-// h_m*dt/phihat_t((n - n0)/n_t); bins b_lo .. b_lo+nb-1 are kept per sensor.
+// h_m*dt/phihat_t((n - n0)/n_t) (hw == nullptr: unit weight instead of
+// h_m*dt); bins b_lo .. b_lo+nb-1 are kept per sensor.
 // ---------------------------------------------------------------------------
 constexpr int kTemporalThreads = 512;
 
@@ -39,8 +40,10 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
         const int m0 = mbase + 2 * pr;
         const bool has1 = m0 + 1 < M;
         const T d = deap[n];
-        const T a = g[size_t(m0) * Nt + n] * hw[m0] * d;
-        const T b = has1 ? g[size_t(m0 + 1) * Nt + n] * hw[m0 + 1] * d : T(0);
+        const T w0 = hw ? hw[m0] : T(1);
+        const T w1 = has1 ? (hw ? hw[m0 + 1] : T(1)) : T(0);
+        const T a = g[size_t(m0) * Nt + n] * w0 * d;
+        const T b = has1 ? g[size_t(m0 + 1) * Nt + n] * w1 * d : T(0);
         return cx<T>{a, b};
       },
       [&](int q, cx<T> v) {
@@ -68,7 +71,7 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
 }
 
 template <typename T>
-hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s) {
+hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted, hipStream_t s) {
   if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t) return hipErrorInvalidValue;
   const int pairs = 1;  // one sensor pair per group measured fastest on MI355X
   const int blocks = (p.M + 2 * pairs - 1) / (2 * pairs);
@@ -76,12 +79,77 @@ hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, hipStream_t s
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T>), lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
-                     static_cast<const T*>(p.hw), static_cast<const T*>(p.deap), as_desc<T>(p.f_nt), p.b_lo, p.nb,
-                     pairs, static_cast<cx<T>*>(Gt));
+                     weighted ? static_cast<const T*>(p.hw) : nullptr, static_cast<const T*>(p.deap),
+                     as_desc<T>(p.f_nt), p.b_lo, p.nb, pairs, static_cast<cx<T>*>(Gt));
   return hipGetLastError();
 }
 
-#define PATK_INST(T) template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, hipStream_t);
+// ---------------------------------------------------------------------------
+// Transpose of k_temporal with unit weights (the forward model's last step):
+//   g[m][n] = a_n Re sum_b Gt'[m][b] exp(+2 pi i b (n - n0)/n_t),
+// a_n = 1/phihat_t((n - n0)/n_t). Two sensors share one inverse FFT: the
+// spectrum Z[k] = (X0[k] + conj X0[-k])/2 + i (X1[k] + conj X1[-k])/2 (band
+// bins placed at b mod n_t) transforms to Re x0 + i Re x1. The band never
+// covers a bin twice (nb <= n_t), so each of the two placement passes
+// writes distinct slots.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal_t(const cx<T>* __restrict__ Gt, int M, int Nt, int n0,
+                                                               const T* __restrict__ deap, FftDesc<T> fd, int b_lo,
+                                                               int nb, T* __restrict__ g) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int n_t = fd.n;
+  const int m0 = 2 * blockIdx.x;
+  const bool has1 = m0 + 1 < M;
+  for (int q = tid; q < n_t; q += nthr) buf[lpos(q)] = cx<T>{T(0), T(0)};
+  __syncthreads();
+  const cx<T>* x0 = Gt + size_t(m0) * nb;
+  const cx<T>* x1 = Gt + size_t(m0 + 1) * nb;
+  const cx<T> zero{T(0), T(0)};
+  for (int i = tid; i < nb; i += nthr) {
+    const int b = b_lo + i;
+    const int pb = b < 0 ? b + n_t : b;
+    const cx<T> a = x0[i], c = has1 ? x1[i] : zero;
+    buf[lpos(pb)] = cx<T>{T(0.5) * (a.x - c.y), T(0.5) * (a.y + c.x)};
+  }
+  __syncthreads();
+  for (int i = tid; i < nb; i += nthr) {
+    const int b = b_lo + i;
+    const int mb = b > 0 ? n_t - b : -b;
+    const cx<T> a = x0[i], c = has1 ? x1[i] : zero;
+    cx<T>& z = buf[lpos(mb)];
+    z = cx<T>{z.x + T(0.5) * (a.x + c.y), z.y + T(0.5) * (c.x - a.y)};
+  }
+  __syncthreads();
+  fft_lds<T, kFftMaxV, true>(buf, fd, 1, lseq(n_t), tid, nthr);
+  __syncthreads();
+  for (int n = tid; n < Nt; n += nthr) {
+    int pos = n - n0;
+    if (pos < 0) pos += n_t;
+    const cx<T> z = buf[lpos(pos)];
+    const T d = deap[n];
+    g[size_t(m0) * Nt + n] = z.x * d;
+    if (has1) g[size_t(m0 + 1) * Nt + n] = z.y * d;
+  }
+}
+
+template <typename T>
+hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s) {
+  if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t || p.nb > p.n_t) return hipErrorInvalidValue;
+  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal_t<T>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_temporal_t<T>, dim3((p.M + 1) / 2), dim3(kTemporalThreads), lds, s,
+                     static_cast<const cx<T>*>(Gt), p.M, p.Nt, p.n0, static_cast<const T*>(p.deap), as_desc<T>(p.f_nt),
+                     p.b_lo, p.nb, g);
+  return hipGetLastError();
+}
+
+#define PATK_INST(T)                                                                      \
+  template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, bool, hipStream_t); \
+  template hipError_t launch_temporal_t<T>(const DevPlan&, const void*, T*, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

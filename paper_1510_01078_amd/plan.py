@@ -109,31 +109,83 @@ class Plan:
         if g.dtype != self.dtype or tuple(g.shape) != (self.m, self.n_t) or not g.is_contiguous():
             raise ValueError(f"traces must be contiguous {self.dtype} of shape {(self.m, self.n_t)}")
 
+    def _check_image(self, f):
+        torch = self._torch
+        if not isinstance(f, torch.Tensor) or f.device != self.device:
+            raise ValueError(f"image must be a tensor on {self.device}")
+        if f.dtype != self.dtype or tuple(f.shape) != self.shape or not f.is_contiguous():
+            raise ValueError(f"image must be contiguous {self.dtype} of shape {self.shape}")
+
+    def _out(self, out, shape, dtype):
+        if out is None:
+            return self._torch.empty(shape, dtype=dtype, device=self.device)
+        if (out.dtype != dtype or tuple(out.shape) != tuple(shape) or not out.is_contiguous()
+                or out.device != self.device):
+            raise ValueError(f"output must be contiguous {dtype} of shape {tuple(shape)} on {self.device}")
+        return out
+
+    def _ws(self, workspace):
+        ws = self.workspace if workspace is None else workspace
+        if ws.device != self.device or ws.numel() * ws.element_size() < self.info["workspace_bytes"]:
+            raise ValueError("workspace too small or on another device")
+        return ws
+
     def reconstruct(self, g, out=None, workspace=None):
         """f = R g (pat_reconstruct). g: [M, Nt] device tensor. Returns [Nx,Ny,Nz]."""
         self._check_handle()
         self._check_traces(g)
-        torch = self._torch
-        if out is None:
-            out = torch.empty(self.shape, dtype=self.dtype, device=self.device)
-        elif out.dtype != self.dtype or tuple(out.shape) != self.shape or not out.is_contiguous():
-            raise ValueError("bad output tensor")
-        ws = self.workspace if workspace is None else workspace
+        out = self._out(out, self.shape, self.dtype)
+        ws = self._ws(workspace)
         N.check(self._lib.pat_reconstruct(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
                                           C.c_void_p(ws.data_ptr()), self._stream()), "pat_reconstruct")
         return out
 
-    def spectrum(self, g, out=None):
+    def spectrum(self, g, out=None, workspace=None):
         """F(K) half spectrum [Nx, Ny, Nz/2+1] complex (pat_spectrum)."""
         self._check_handle()
         self._check_traces(g)
-        torch = self._torch
         shp = (self.shape[0], self.shape[1], self.shape[2] // 2 + 1)
-        if out is None:
-            out = torch.empty(shp, dtype=self.cdtype, device=self.device)
+        out = self._out(out, shp, self.cdtype)
+        ws = self._ws(workspace)
         N.check(self._lib.pat_spectrum(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
-                                       C.c_void_p(self.workspace.data_ptr()), self._stream()), "pat_spectrum")
+                                       C.c_void_p(ws.data_ptr()), self._stream()), "pat_spectrum")
         return out
+
+    def forward(self, f, out=None, workspace=None):
+        """g = A f (pat_forward): image [Nx,Ny,Nz] -> traces [M, Nt]."""
+        self._check_handle()
+        self._check_image(f)
+        out = self._out(out, (self.m, self.n_t), self.dtype)
+        ws = self._ws(workspace)
+        N.check(self._lib.pat_forward(self._handle, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(ws.data_ptr()), self._stream()), "pat_forward")
+        return out
+
+    def adjoint(self, g, out=None, workspace=None):
+        """f = A* g (pat_adjoint): traces [M, Nt] -> image [Nx,Ny,Nz]."""
+        self._check_handle()
+        self._check_traces(g)
+        out = self._out(out, self.shape, self.dtype)
+        ws = self._ws(workspace)
+        N.check(self._lib.pat_adjoint(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(ws.data_ptr()), self._stream()), "pat_adjoint")
+        return out
+
+    def forward_dxy(self, f, axis, out=None, workspace=None):
+        """d(A f)/d(x_m) (axis 0) or d(A f)/d(y_m) (axis 1) per trace (pat_forward_dxy)."""
+        self._check_handle()
+        self._check_image(f)
+        out = self._out(out, (self.m, self.n_t), self.dtype)
+        ws = self._ws(workspace)
+        N.check(self._lib.pat_forward_dxy(self._handle, C.c_void_p(f.data_ptr()), int(axis),
+                                          C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()), self._stream()),
+                "pat_forward_dxy")
+        return out
+
+    @property
+    def sensor_xy(self):
+        """The sensor positions the plan was built for (host copy, [M, 2])."""
+        return self._xy.copy()
 
     def timing_begin(self, max_calls: int):
         self._check_handle()

@@ -107,5 +107,7 @@ def test_null_arguments():
     assert lib.pat_spectrum(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_forward(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_adjoint(None, None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_forward_dxy(None, None, 0, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_forward_dxy(None, None, 2, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_timing_begin(None, 4) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_plan_desc_init(None) == N.PAT_ERR_INVALID_ARGUMENT
