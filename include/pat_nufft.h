@@ -80,6 +80,14 @@ typedef enum {
   PAT_KERNEL_KAISER_BESSEL = 1   /* Kaiser-Bessel, the window named in Section 3.1 */
 } pat_kernel;
 
+/* Temporal interpolation at omega(K) (the NER step, Section 3.1). */
+typedef enum {
+  PAT_INTERP_WINDOW = 0,  /* NER-NUFFT: deapodised, centred FFT and the window's width_t taps */
+  PAT_INTERP_LINEAR = 1   /* comparison baseline of Section 5.1 (Table 1): zeros appended after the
+                             trace, FFT of length smooth(sigma_t*Nt), linear interpolation between the
+                             two nearest bins; width_t is ignored and sigma_t may be 1 */
+} pat_temporal_interp;
+
 typedef struct pat_plan_desc {
   int32_t n_sensors;         /* M >= 1 */
   int32_t n_t;               /* Nt >= 2, samples per trace */
@@ -92,10 +100,11 @@ typedef struct pat_plan_desc {
   double lx, ly, lz;         /* extents X, Y, Z in metres, > 0 */
   double sigma_xy;           /* lateral oversampling factor, >= 1.1 (grid = smooth(sigma*N)) */
   int32_t width_xy;          /* lateral window footprint w in grid points, even, 2..16 */
-  double sigma_t;            /* temporal oversampling factor, >= 1.1 */
+  double sigma_t;            /* temporal oversampling factor, >= 1.1 (>= 1.0 for PAT_INTERP_LINEAR) */
   int32_t width_t;           /* temporal window footprint, even, 2..16 */
   pat_kernel kernel;
   pat_precision precision;
+  pat_temporal_interp temporal_interp;
   /* Optional device allocator (e.g. a framework's caching allocator). Both
    * NULL: the library uses hipMalloc/hipFree. alloc must return memory on the
    * current device aligned to at least 256 bytes, or NULL on failure. */
@@ -122,8 +131,8 @@ typedef struct pat_plan_info {
   int32_t rounds;            /* spread / x-FFT rounds per call */
 } pat_plan_info;
 
-/* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, NULL
- * pointers, zero sizes. Returns PAT_ERR_INVALID_ARGUMENT if desc is NULL. */
+/* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, window
+ * interpolation, NULL pointers, zero sizes. Returns PAT_ERR_INVALID_ARGUMENT if desc is NULL. */
 pat_status pat_plan_desc_init(pat_plan_desc* desc);
 
 /* Build a plan for one sensor geometry and output grid (the precomputation

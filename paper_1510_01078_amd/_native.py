@@ -20,6 +20,7 @@ PAT_ERR_NOT_IMPLEMENTED = 5
 
 PAT_FP64, PAT_FP32, PAT_FP32_KAHAN = 0, 1, 2
 PAT_KERNEL_GAUSSIAN, PAT_KERNEL_KAISER_BESSEL = 0, 1
+PAT_INTERP_WINDOW, PAT_INTERP_LINEAR = 0, 1
 PAT_TIMING_STAGES = 6
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -46,6 +47,7 @@ class PlanDesc(C.Structure):
         ("width_t", C.c_int32),
         ("kernel", C.c_int),
         ("precision", C.c_int),
+        ("temporal_interp", C.c_int),
         ("alloc", ALLOC_FN),
         ("free", FREE_FN),
         ("alloc_ctx", C.c_void_p),

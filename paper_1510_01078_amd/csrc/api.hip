@@ -123,7 +123,10 @@ pat_status validate(const pat_plan_desc* d) {
     if (n < 4 || (n % 2) != 0) return PAT_ERR_INVALID_ARGUMENT;
   for (double L : {d->lx, d->ly, d->lz})
     if (!(L > 0.0) || !std::isfinite(L)) return PAT_ERR_INVALID_ARGUMENT;
-  if (!(d->sigma_xy >= 1.1 && d->sigma_xy <= 4.0) || !(d->sigma_t >= 1.1 && d->sigma_t <= 4.0))
+  if (d->temporal_interp != PAT_INTERP_WINDOW && d->temporal_interp != PAT_INTERP_LINEAR)
+    return PAT_ERR_INVALID_ARGUMENT;
+  const double sigma_t_min = d->temporal_interp == PAT_INTERP_LINEAR ? 1.0 : 1.1;
+  if (!(d->sigma_xy >= 1.1 && d->sigma_xy <= 4.0) || !(d->sigma_t >= sigma_t_min && d->sigma_t <= 4.0))
     return PAT_ERR_INVALID_ARGUMENT;
   if (d->width_xy < 2 || d->width_xy > 16 || (d->width_xy % 2) || d->width_t < 2 || d->width_t > 16 ||
       (d->width_t % 2))
@@ -171,10 +174,13 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.Nz = d.nz;
   dp.n_x = next_smooth_even(d.sigma_xy * d.nx);
   dp.n_y = next_smooth_even(d.sigma_xy * d.ny);
+  const bool linear_t = d.temporal_interp == PAT_INTERP_LINEAR;
   dp.n_t = next_smooth_even(d.sigma_t * Nt);
-  dp.n0 = Nt / 2;
+  // window form: samples centred on n0 = Nt/2; linear baseline: zeros appended
+  // after the trace (time origin 0) and two taps
+  dp.n0 = linear_t ? 0 : Nt / 2;
   dp.w_xy = d.width_xy;
-  dp.w_t = d.width_t;
+  dp.w_t = linear_t ? 2 : d.width_t;
   dp.kahan = d.precision == PAT_FP32_KAHAN;
   const size_t cxb = 2 * sizeof(T);
   // FFT lengths the LDS kernels handle: one padded sequence per work-group must fit the device's LDS
@@ -225,9 +231,9 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   std::vector<double> hw(M);
   for (int m = 0; m < M; ++m) hw[m] = (d.sensor_h ? d.sensor_h[m] : d.lx * d.ly / M) * d.dt;
   const size_t o_hw = add_real<T>(blob, hw);
-  // temporal deapodisation 1/phihat_t((n - n0)/n_t)
+  // temporal deapodisation 1/phihat_t((n - n0)/n_t) (none for the linear baseline)
   std::vector<double> deap(Nt);
-  for (int n = 0; n < Nt; ++n) deap[n] = 1.0 / wt.phihat(double(n - dp.n0) / dp.n_t);
+  for (int n = 0; n < Nt; ++n) deap[n] = linear_t ? 1.0 : 1.0 / wt.phihat(double(n - dp.n0) / dp.n_t);
   const size_t o_deap = add_real<T>(blob, deap);
   // sensor footprints and weights on the oversampled lateral grid
   const int w = dp.w_xy;
@@ -309,6 +315,12 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   for (; deg <= 24; ++deg)
     if (pathost::fit_tap_polynomials(wt, deg, coef) <= tol) break;
   if (deg > 24) deg = 24;
+  if (linear_t) {
+    // linear interpolation between bins floor(s) and floor(s)+1 with
+    // weights 1 - frac and frac; in y = 2 frac - 1 these are (1 -+ y)/2
+    deg = 1;
+    coef = {0.5, -0.5, 0.5, 0.5};
+  }
   dp.hdeg = deg;
   const size_t o_hc = add_real<T>(blob, coef);
   // twiddles

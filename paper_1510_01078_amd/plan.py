@@ -24,13 +24,16 @@ class Plan:
     Parameters mirror pat_plan_desc: sensor_xy [M,2] (metres, plane-centred),
     sensor_h [M] (m^2, None for X*Y/M), n_t, dt, c, shape (Nx,Ny,Nz),
     extent (X,Y,Z), lateral/temporal oversampling and window widths, window
-    kernel ('kaiser_bessel' or 'gaussian') and precision ('fp32',
-    'fp32_kahan' or 'fp64'). The plan lives on `device` (default: the
+    kernel ('kaiser_bessel' or 'gaussian'), precision ('fp32',
+    'fp32_kahan' or 'fp64') and temporal interpolation ('window': the
+    NER-NUFFT; 'linear': the zero-padded FFT with linear interpolation that
+    the paper compares against). The plan lives on `device` (default: the
     current CUDA/HIP device) and uses torch's current stream there.
     """
 
     def __init__(self, sensor_xy, n_t, dt, c, shape, extent, sensor_h=None, sigma_xy=2.0, width_xy=8,
-                 sigma_t=2.0, width_t=8, kernel="kaiser_bessel", precision="fp32", device=None):
+                 sigma_t=2.0, width_t=8, kernel="kaiser_bessel", precision="fp32", device=None,
+                 temporal_interp="window"):
         import torch
 
         self._torch = torch
@@ -67,6 +70,7 @@ class Plan:
         d.width_t = int(width_t)
         d.kernel = _KERNELS[kernel]
         d.precision = _PRECISIONS[precision]
+        d.temporal_interp = {"window": N.PAT_INTERP_WINDOW, "linear": N.PAT_INTERP_LINEAR}[temporal_interp]
 
         self._blocks = {}
         dev = self.device

@@ -65,6 +65,8 @@ def _desc(xy, **kw):
     ("width_xy", 20, N.PAT_ERR_UNSUPPORTED),
     ("kernel", 7, N.PAT_ERR_INVALID_ARGUMENT),
     ("precision", 9, N.PAT_ERR_INVALID_ARGUMENT),
+    ("temporal_interp", 2, N.PAT_ERR_INVALID_ARGUMENT),
+    ("sigma_t", 1.0, N.PAT_ERR_INVALID_ARGUMENT),
 ])
 def test_descriptor_validation(field, value, expect):
     lib = N.load()
@@ -73,6 +75,20 @@ def test_descriptor_validation(field, value, expect):
     h = C.c_void_p(1234)
     assert lib.nufft_plan(C.byref(d), None, C.byref(h)) == expect
     assert h.value is None
+
+
+def test_linear_baseline_accepts_sigma_one():
+    """sigma_t = 1 is refused for the window form but passes validation for
+    the linear baseline (the call then needs a device: without a GPU it
+    stops at the device query, after validation)."""
+    lib = N.load()
+    xy = np.zeros((4, 2))
+    d = _desc(xy, sigma_t=1.0, temporal_interp=N.PAT_INTERP_LINEAR)
+    h = C.c_void_p()
+    st = lib.nufft_plan(C.byref(d), None, C.byref(h))
+    assert st != N.PAT_ERR_INVALID_ARGUMENT
+    if st == N.PAT_OK:
+        lib.nufft_plan_destroy(h)
 
 
 def test_sensor_outside_plane_rejected():
