@@ -202,6 +202,41 @@ pat_status pat_adjoint(pat_plan* plan, const void* g, void* f, void* workspace, 
  * and errors as pat_forward; PAT_ERR_INVALID_ARGUMENT for another axis. */
 pat_status pat_forward_dxy(pat_plan* plan, const void* f, int32_t axis, void* g, void* workspace, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched reconstruction: count (1..64) independent problems, each with its
+ * own descriptor (geometry, trace length, output grid, window settings; all
+ * with the same element type), reconstructed with one kernel launch per
+ * stage for the whole batch: every stage's work items are the blocks of all
+ * problems, so small problems share the device instead of running one after
+ * another. Results equal pat_reconstruct's for each problem bit for bit.
+ *
+ * pat_batch_create builds one plan per descriptor (as nufft_plan), uploads
+ * per-problem argument tables and allocates the batch's workspace through
+ * descs[0]'s allocator (or hipMalloc), then synchronises `stream`. The batch
+ * owns its plans, tables and workspace, so calls on one batch must not
+ * overlap in time (they share the workspace).
+ * ------------------------------------------------------------------------ */
+typedef struct pat_batch pat_batch;
+
+pat_status pat_batch_create(const pat_plan_desc* descs, int32_t count, void* stream, pat_batch** out);
+
+/* Plan of problem `index` (read-only, e.g. for pat_plan_get_info). */
+pat_status pat_batch_get_plan(const pat_batch* batch, int32_t index, const pat_plan** plan);
+
+/* Grid of the batched launches: 0 (default) launches one work-group per work
+ * item; blocks > 0 launches at most that many work-groups, each looping over
+ * the work items (a persistent launch). Results do not depend on it. */
+pat_status pat_batch_set_grid(pat_batch* batch, int32_t blocks);
+
+/* f[p] = R g[p] for every problem p: g and f are HOST arrays of `count`
+ * DEVICE pointers with the layouts of pat_reconstruct. Enqueues eight kernels
+ * on `stream` (no allocation, no synchronisation), so the call can be
+ * captured into a HIP graph. Inputs and outputs must not overlap. */
+pat_status pat_batch_reconstruct(pat_batch* batch, const void* const* g, void* const* f, void* stream);
+
+/* Synchronises the device, then releases the batch. NULL is ignored. */
+pat_status pat_batch_destroy(pat_batch* batch);
+
 /* Per-stage device timing with HIP events recorded on the call's stream.
  * pat_timing_begin(plan, n) creates events for up to n subsequent compute
  * calls (allocation happens here, not in the compute calls). pat_timing_end

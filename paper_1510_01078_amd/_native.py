@@ -22,6 +22,7 @@ PAT_FP64, PAT_FP32, PAT_FP32_KAHAN = 0, 1, 2
 PAT_KERNEL_GAUSSIAN, PAT_KERNEL_KAISER_BESSEL = 0, 1
 PAT_INTERP_WINDOW, PAT_INTERP_LINEAR = 0, 1
 PAT_TIMING_STAGES = 6
+PAT_BATCH_MAX = 64
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -84,6 +85,11 @@ SIGNATURES = {
     "pat_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_forward_dxy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pat_batch_create": (C.c_int, [C.POINTER(PlanDesc), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pat_batch_get_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
+    "pat_batch_set_grid": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pat_batch_reconstruct": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
+    "pat_batch_destroy": (C.c_int, [C.c_void_p]),
     "pat_timing_begin": (C.c_int, [C.c_void_p, C.c_int32]),
     "pat_timing_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
     "pat_status_str": (C.c_char_p, [C.c_int]),

@@ -12,12 +12,13 @@
 
 #include "kernels.hpp"
 #include "pat_nufft.h"
+#include "plan_internal.hpp"
 #include "window.hpp"
+
+using namespace patint;
 
 namespace {
 
-constexpr size_t kAlign = 256;
-inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 inline bool smooth235(long n) {
   if (n < 1) return false;
@@ -91,26 +92,6 @@ size_t add_twiddles(HostBlob& b, int n) {
 
 }  // namespace
 
-struct pat_plan {
-  pat_plan_desc d;
-  int device = 0;
-  bool fp64 = false;
-  patk::DevPlan dp;
-  void* dev = nullptr;
-  size_t dev_bytes = 0;
-  size_t off_B = 0;     // workspace regions: A at 0 (grid chunk / lateral spectra),
-  size_t off_C = 0;     // B at off_B (x rows / spectrum), C at off_C (per-sensor bins)
-  size_t ws_bytes = 0;
-  int64_t spread_pairs = 0;
-  bool forward_ok = false;  // the forward model's per-column LDS fits the device
-  // timing: per recorded call, marks_per_call events; mark i > 0 closes the
-  // interval of stage ev_stage[i] that began at mark i-1
-  std::vector<hipEvent_t> ev;
-  std::vector<int> ev_stage;
-  int marks_per_call = 0;
-  int ev_max = 0;
-  int ev_used = 0;
-};
 
 namespace {
 
@@ -144,23 +125,7 @@ pat_status validate(const pat_plan_desc* d) {
   return PAT_OK;
 }
 
-void* dev_alloc(const pat_plan_desc& d, size_t bytes) {
-  if (d.alloc) return d.alloc(bytes, d.alloc_ctx);
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  return p;
-}
 
-void dev_free(const pat_plan_desc& d, void* p) {
-  if (!p) return;
-  if (d.free)
-    d.free(p, d.alloc_ctx);
-  else
-    (void)hipFree(p);
-}
 
 template <typename T>
 pat_status build_tables(pat_plan* P, hipStream_t stream) {
@@ -393,24 +358,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   return PAT_OK;
 }
 
-pat_status to_status(hipError_t e) { return e == hipSuccess ? PAT_OK : PAT_ERR_HIP; }
 
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = true;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) {
-      ok = false;
-      prev = -1;
-      return;
-    }
-    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
 
 struct Marker {
   pat_plan* P;

@@ -1,0 +1,277 @@
+// Batched reconstruction: up to kBatchMax independent problems (each its own
+// sensor geometry, trace length and output grid) reconstructed with one
+// launch per stage. Every stage's work items are the blocks of all problems
+// (problem after problem); per-problem arguments are uploaded once at
+// creation, so a call only enqueues eight kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels_common.hpp"
+#include "pat_nufft.h"
+#include "plan_internal.hpp"
+
+using namespace patint;
+
+namespace {
+constexpr int kStages = 8;  // temporal, spread, fft x, fft y, gather, inverse x, inverse y, c2r z
+}
+
+struct pat_batch {
+  int count = 0;
+  int device = 0;
+  bool fp64 = false;
+  pat_plan* plans[patk::kBatchMax] = {};
+  pat_plan_desc alloc_desc{};  // allocator used for the batch's own memory
+  void* tables = nullptr;      // argument tables and prefix sums
+  void* ws = nullptr;          // workspace of every problem
+  size_t ws_bytes = 0;
+  size_t table_bytes = 0;
+  patk::BatchStage st[kStages];
+};
+
+namespace {
+
+struct Blob {
+  std::vector<unsigned char> bytes;
+  size_t add(const void* src, size_t n) {
+    const size_t off = align_up(bytes.size());
+    bytes.resize(off + n);
+    if (n) std::memcpy(bytes.data() + off, src, n);
+    return off;
+  }
+};
+
+void destroy_batch(pat_batch* B) {
+  if (!B) return;
+  {
+    DeviceGuard guard(B->device);
+    (void)hipDeviceSynchronize();
+    dev_free(B->alloc_desc, B->ws);
+    dev_free(B->alloc_desc, B->tables);
+  }
+  for (int i = 0; i < B->count; ++i) nufft_plan_destroy(B->plans[i]);
+  delete B;
+}
+
+template <typename T>
+pat_status build_batch(pat_batch* B, hipStream_t stream) {
+  using patk::cx;
+  const int P = B->count;
+  const size_t c = sizeof(cx<T>);
+  const patk::FftCfg cfg = patk::fft_cfg();
+  // workspace per problem: A = grid U (all bins) / lateral spectra, B = x rows / spectrum, C = band values
+  std::vector<size_t> offA(P), offB(P), offC(P);
+  size_t total = 0;
+  for (int p = 0; p < P; ++p) {
+    const patk::DevPlan& d = B->plans[p]->dp;
+    const size_t lh = size_t(d.Nz / 2 + 1);
+    const size_t a = std::max(size_t(d.nb) * d.n_y * d.n_x * c, size_t(d.Nx) * d.Ny * d.nb * c);
+    const size_t b = std::max(size_t(d.nb) * d.Nx * d.n_y * c, size_t(d.Nx) * d.Ny * lh * c);
+    const size_t cc = size_t(d.M) * d.nb * c;
+    offA[p] = total;
+    total += align_up(a);
+    offB[p] = total;
+    total += align_up(b);
+    offC[p] = total;
+    total += align_up(cc);
+  }
+  B->ws_bytes = total;
+  B->ws = dev_alloc(B->alloc_desc, total);
+  if (!B->ws) return PAT_ERR_ALLOC;
+  unsigned char* ws = static_cast<unsigned char*>(B->ws);
+
+  std::vector<patk::TemporalBA> a0(P);
+  std::vector<patk::SpreadBA> a1(P);
+  std::vector<patk::FftXBA> a2(P);
+  std::vector<patk::FftYBA> a3(P);
+  std::vector<patk::GatherBA> a4(P);
+  std::vector<patk::CfftBA> a5(P), a6(P);
+  std::vector<patk::C2rBA> a7(P);
+  std::vector<int> pre[kStages];
+  for (auto& v : pre) v.assign(P + 1, 0);
+  size_t lds[kStages] = {};
+  const int kFft = patk::kFftMaxV * cfg.threads;
+  for (int p = 0; p < P; ++p) {
+    const patk::DevPlan& d = B->plans[p]->dp;
+    void* A = ws + offA[p];
+    void* Bw = ws + offB[p];
+    void* C = ws + offC[p];
+    const int Lh = d.Nz / 2 + 1;
+    if (d.n_t > patk::kFftMaxV * 512) return PAT_ERR_UNSUPPORTED;
+    // stage 0: temporal FFT, one block per sensor pair
+    a0[p] = patk::TemporalBA{d.hw, d.deap, patk::as_view(d.f_nt), d.M, d.Nt, d.n0, d.b_lo, d.nb, C};
+    pre[0][p + 1] = (d.M + 1) / 2;
+    lds[0] = std::max(lds[0], size_t(patk::lseq(d.n_t)) * c);
+    // stage 1: spread, all bins in one round
+    const int nchunks = (d.nb + 15) / 16;
+    a1[p] = patk::SpreadBA{C, d.tile_off, d.tile_sens, d.sbx, d.sby, d.swx, d.swy, d.nb, d.w_xy,
+                           d.n_x, d.n_y, d.tiles_x, nchunks, A};
+    pre[1][p + 1] = d.tiles_x * d.tiles_y * nchunks;
+    // stage 2: FFT along x
+    const int rows = patk::fft_batch<T>(d.n_x, cfg.threads, cfg.cap);
+    if (rows * d.n_x > kFft || rows * d.Nx > kFft) return PAT_ERR_UNSUPPORTED;
+    const int gx2 = (d.n_y + rows - 1) / rows;
+    a2[p] = patk::FftXBA{A, patk::as_view(d.f_nx), d.n_y, d.Nx, rows, gx2, Bw};
+    pre[2][p + 1] = gx2 * d.nb;
+    lds[2] = std::max(lds[2], size_t(rows) * patk::lseq(d.n_x) * c);
+    // stage 3: FFT along y with deconvolution
+    const int bins = patk::fft_batch<T>(d.n_y, cfg.threads, cfg.cap);
+    if (bins * d.n_y > kFft || bins * d.Ny > kFft) return PAT_ERR_UNSUPPORTED;
+    const int gx3 = (d.nb + bins - 1) / bins;
+    a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A};
+    pre[3][p + 1] = gx3 * d.Nx;
+    lds[3] = std::max(lds[3], size_t(bins) * patk::lseq(d.n_y) * c);
+    // stage 4: temporal interpolation and weight (image-ready spectrum)
+    a4[p] = patk::GatherBA{A, d.hcoef, d.nb, d.b_lo, d.Nx, d.Ny, d.Nz, d.w_t, d.hdeg,
+                           d.s_per_k, d.kxu, d.kyu, d.kzu, d.two_c, d.n0_over_nt, d.inv_vol, Bw};
+    pre[4][p + 1] = int((size_t(d.Nx) * d.Ny * Lh + 255) / 256);
+    // stages 5, 6: inverse transforms along x and y (in place on the spectrum)
+    const int lcx = patk::fft_batch<T>(d.Nx, cfg.threads, cfg.cap);
+    const int gx5 = (Lh + lcx - 1) / lcx;
+    a5[p] = patk::CfftBA{Bw, patk::as_view(d.f_Nx), d.Ny, Lh, lcx, gx5};
+    pre[5][p + 1] = gx5 * d.Ny;
+    lds[5] = std::max(lds[5], size_t(lcx) * patk::lseq(d.Nx) * c);
+    const int lcy = patk::fft_batch<T>(d.Ny, cfg.threads, cfg.cap);
+    const int gx6 = (Lh + lcy - 1) / lcy;
+    a6[p] = patk::CfftBA{Bw, patk::as_view(d.f_Ny), d.Ny, Lh, lcy, gx6};
+    pre[6][p + 1] = gx6 * d.Nx;
+    lds[6] = std::max(lds[6], size_t(lcy) * patk::lseq(d.Ny) * c);
+    // stage 7: complex-to-real along z into the caller's image
+    const int rz = patk::fft_batch<T>(d.Nz, cfg.threads, cfg.cap);
+    const long long nrows = (long long)d.Nx * d.Ny;
+    a7[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
+    pre[7][p + 1] = int((nrows + rz - 1) / rz);
+    lds[7] = std::max(lds[7], size_t(rz) * patk::lseq(d.Nz) * c);
+  }
+  for (auto& v : pre) {
+    for (int p = 0; p < P; ++p) {
+      const long long next = (long long)v[p] + v[p + 1];
+      if (next > 0x7fffffffLL) return PAT_ERR_UNSUPPORTED;
+      v[p + 1] = int(next);
+    }
+  }
+  Blob blob;
+  size_t oa[kStages], op[kStages];
+  oa[0] = blob.add(a0.data(), a0.size() * sizeof(a0[0]));
+  oa[1] = blob.add(a1.data(), a1.size() * sizeof(a1[0]));
+  oa[2] = blob.add(a2.data(), a2.size() * sizeof(a2[0]));
+  oa[3] = blob.add(a3.data(), a3.size() * sizeof(a3[0]));
+  oa[4] = blob.add(a4.data(), a4.size() * sizeof(a4[0]));
+  oa[5] = blob.add(a5.data(), a5.size() * sizeof(a5[0]));
+  oa[6] = blob.add(a6.data(), a6.size() * sizeof(a6[0]));
+  oa[7] = blob.add(a7.data(), a7.size() * sizeof(a7[0]));
+  for (int i = 0; i < kStages; ++i) op[i] = blob.add(pre[i].data(), pre[i].size() * sizeof(int));
+  B->table_bytes = align_up(blob.bytes.size());
+  B->tables = dev_alloc(B->alloc_desc, B->table_bytes);
+  if (!B->tables) return PAT_ERR_ALLOC;
+  if (hipMemcpyAsync(B->tables, blob.bytes.data(), blob.bytes.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return PAT_ERR_HIP;
+  }
+  unsigned char* tb = static_cast<unsigned char*>(B->tables);
+  const bool kahan = B->plans[0]->dp.kahan;
+  for (int i = 0; i < kStages; ++i) {
+    B->st[i].args = tb + oa[i];
+    B->st[i].prefix = reinterpret_cast<const int*>(tb + op[i]);
+    B->st[i].nprob = P;
+    B->st[i].total = pre[i][P];
+    B->st[i].lds = lds[i];
+    B->st[i].grid = 0;
+    B->st[i].kahan = kahan;
+  }
+  return PAT_OK;
+}
+
+template <typename T>
+pat_status run_batch(pat_batch* B, const patk::BatchIO& io, hipStream_t s) {
+  hipError_t e;
+  if ((e = patk::launch_temporal_batch<T>(B->st[0], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_spread_batch<T>(B->st[1], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_fft_x_batch<T>(B->st[2], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_fft_y_batch<T>(B->st[3], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_gather_batch<T>(B->st[4], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_cfft_x_inv_batch<T>(B->st[5], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_cfft_y_inv_batch<T>(B->st[6], io, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_c2r_z_batch<T>(B->st[7], io, s)) != hipSuccess) return to_status(e);
+  return PAT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pat_status pat_batch_create(const pat_plan_desc* descs, int32_t count, void* stream, pat_batch** out) {
+  if (!out) return PAT_ERR_INVALID_ARGUMENT;
+  *out = nullptr;
+  if (!descs || count < 1 || count > patk::kBatchMax) return PAT_ERR_INVALID_ARGUMENT;
+  for (int i = 1; i < count; ++i) {
+    const bool fp64_i = descs[i].precision == PAT_FP64, fp64_0 = descs[0].precision == PAT_FP64;
+    if (fp64_i != fp64_0 || (descs[i].precision == PAT_FP32_KAHAN) != (descs[0].precision == PAT_FP32_KAHAN))
+      return PAT_ERR_INVALID_ARGUMENT;
+  }
+  pat_batch* B = new (std::nothrow) pat_batch();
+  if (!B) return PAT_ERR_ALLOC;
+  if (hipGetDevice(&B->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete B;
+    return PAT_ERR_HIP;
+  }
+  B->alloc_desc = descs[0];
+  B->alloc_desc.sensor_xy = nullptr;
+  B->alloc_desc.sensor_h = nullptr;
+  B->fp64 = descs[0].precision == PAT_FP64;
+  for (int i = 0; i < count; ++i) {
+    pat_status st = nufft_plan(&descs[i], stream, &B->plans[i]);
+    if (st != PAT_OK) {
+      destroy_batch(B);
+      return st;
+    }
+    B->count = i + 1;
+  }
+  const pat_status st = B->fp64 ? build_batch<double>(B, static_cast<hipStream_t>(stream))
+                                : build_batch<float>(B, static_cast<hipStream_t>(stream));
+  if (st != PAT_OK) {
+    destroy_batch(B);
+    return st;
+  }
+  *out = B;
+  return PAT_OK;
+}
+
+pat_status pat_batch_get_plan(const pat_batch* B, int32_t index, const pat_plan** plan) {
+  if (!B || !plan || index < 0 || index >= B->count) return PAT_ERR_INVALID_ARGUMENT;
+  *plan = B->plans[index];
+  return PAT_OK;
+}
+
+pat_status pat_batch_set_grid(pat_batch* B, int32_t blocks) {
+  if (!B || blocks < 0) return PAT_ERR_INVALID_ARGUMENT;
+  for (auto& s : B->st) s.grid = blocks;
+  return PAT_OK;
+}
+
+pat_status pat_batch_reconstruct(pat_batch* B, const void* const* g, void* const* f, void* stream) {
+  if (!B || !g || !f) return PAT_ERR_INVALID_ARGUMENT;
+  patk::BatchIO io{};
+  for (int p = 0; p < B->count; ++p) {
+    if (!g[p] || !f[p]) return PAT_ERR_INVALID_ARGUMENT;
+    io.in[p] = g[p];
+    io.out[p] = f[p];
+  }
+  DeviceGuard guard(B->device);
+  if (!guard.ok) return PAT_ERR_HIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return B->fp64 ? run_batch<double>(B, io, s) : run_batch<float>(B, io, s);
+}
+
+pat_status pat_batch_destroy(pat_batch* B) {
+  destroy_batch(B);
+  return PAT_OK;
+}
+
+}  // extern "C"

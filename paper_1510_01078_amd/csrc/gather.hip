@@ -60,13 +60,13 @@ __device__ __forceinline__ T tap_weight(const T* __restrict__ hcoef, int t, int 
 enum { MODE_IMAGE = 0, MODE_PHYSICAL = 1, MODE_ADJOINT = 2 };
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
-                                                double s_per_k, double kxu, double kyu, double kzu, double two_c,
-                                                double n0_over_nt, double scale, int wt, int deg,
-                                                const T* __restrict__ hcoef, cx<T>* __restrict__ Fh) {
+__device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                            double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                            double n0_over_nt, double scale, int wt, int deg,
+                                            const T* __restrict__ hcoef, cx<T>* __restrict__ Fh, int bx) {
   const int Lh = Nz / 2 + 1;
   const long long total = (long long)Nx * Ny * Lh;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long idx = (long long)bx * blockDim.x + threadIdx.x;
   if (idx >= total) return;
   const int l = int(idx % Lh);
   const long long col = idx / Lh;
@@ -107,6 +107,15 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, in
   if (MODE == MODE_PHYSICAL && ((jj + kk) & 1)) wgt = -wgt;
   const cx<T> ph{T(wgt * tp.cs), T(wgt * tp.sn)};
   Fh[idx] = cmul(acc, ph);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                                double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                                double n0_over_nt, double scale, int wt, int deg,
+                                                const T* __restrict__ hcoef, cx<T>* __restrict__ Fh) {
+  gather_body<T, MODE>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt, deg, hcoef, Fh,
+                       blockIdx.x);
 }
 
 template <typename T>
@@ -244,10 +253,34 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
   return hipGetLastError();
 }
 
+// Batched form of the reconstruction's interpolation (image-ready spectrum).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const GatherBA a = args[p];
+    gather_body<T, MODE_IMAGE>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k, a.kxu, a.kyu,
+                               a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg, static_cast<const T*>(a.hcoef),
+                               static_cast<cx<T>*>(a.Fh), w - prefix[p]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gather_batch<T>), dim3(batch_grid(st)), dim3(256), st.lds, s, static_cast<const GatherBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
 #define PATK_INST(T)                                                                     \
   template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
   template size_t scatter_lds_bytes<T>(const DevPlan&);                                  \
-  template hipError_t launch_scatter<T>(const DevPlan&, const void*, void*, int, hipStream_t);
+  template hipError_t launch_scatter<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
+  template hipError_t launch_gather_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -14,15 +14,15 @@ namespace patk {
 // along x and along y, then a complex-to-real transform along z.
 // ---------------------------------------------------------------------------
 template <typename T, bool INV>
-__global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
-                                                      FftDesc<T> fd, int wm) {
+__device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
+                                            FftDesc<T> fd, int wm, int bx, int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Nx = fd.n;
   const int bstride = lseq(Nx);
-  const int kk = blockIdx.y;
-  const int l0 = blockIdx.x * lchunk;
+  const int kk = by;
+  const int l0 = bx * lchunk;
   const int nl = min(lchunk, Lh - l0);
   const FastDiv div_nl(nl);
   staged_copy<kFftMaxV>(
@@ -51,14 +51,21 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, i
 }
 
 template <typename T, bool INV>
-__global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm) {
+__global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
+                                                      FftDesc<T> fd, int wm) {
+  cfft_x_body<T, INV>(F, Ny, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm, int bx,
+                                            int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Ny = fd.n;
   const int bstride = lseq(Ny);
-  const int jj = blockIdx.y;
-  const int l0 = blockIdx.x * lchunk;
+  const int jj = by;
+  const int l0 = bx * lchunk;
   const int nl = min(lchunk, Lh - l0);
   cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
   const FastDiv div_nl(nl);
@@ -87,16 +94,22 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, i
       });
 }
 
+template <typename T, bool INV>
+__global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd,
+                                                      int wm) {
+  cfft_y_body<T, INV>(F, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+}
+
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
-                                                     FftDesc<T> fd, T* __restrict__ f, int wm) {
+__device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long long nrows, int rows,
+                                           FftDesc<T> fd, T* __restrict__ f, int wm, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int Nz = fd.n;
   const int Lh = Nz / 2 + 1;
   const int bstride = lseq(Nz);
-  const long long r0 = (long long)blockIdx.x * rows;
+  const long long r0 = (long long)bx * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
   const FastDiv div_lh(Lh), div_nz(Nz);
   staged_copy<kFftMaxV>(
@@ -117,6 +130,12 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
         return buf[r * bstride + lpos(q - r * Nz)].x;
       },
       [&](int q, T v) { f[r0 * Nz + q] = v; });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
+                                                     FftDesc<T> fd, T* __restrict__ f, int wm) {
+  c2r_z_body<T>(F, nrows, rows, fd, f, wm, blockIdx.x);
 }
 
 // Transpose of k_c2r_z for the forward model: real rows f[r][e] ->
@@ -209,9 +228,78 @@ hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t 
   return launch_xy<T, false>(p, D, false, s);
 }
 
+// Batched forms of the inverse passes.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_cfft_x_inv_batch(const CfftBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const CfftBA a = args[p];
+    const int local = w - prefix[p];
+    const int by = local / a.gx;
+    cfft_x_body<T, true>(static_cast<cx<T>*>(a.F), a.Ny, a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const CfftBA a = args[p];
+    const int local = w - prefix[p];
+    const int by = local / a.gx;
+    cfft_y_body<T, true>(static_cast<cx<T>*>(a.F), a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const C2rBA a = args[p];
+    c2r_z_body<T>(static_cast<const cx<T>*>(a.F), a.nrows, a.rows, view_desc<T>(a.fd), static_cast<T*>(io.out[p]), 0,
+                  w - prefix[p]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_cfft_x_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_x_inv_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cfft_x_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const CfftBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cfft_y_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_y_inv_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cfft_y_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const CfftBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_c2r_z_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_c2r_z_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const C2rBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
 #define PATK_INST(T)                                                                \
   template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t); \
-  template hipError_t launch_forward3d<T>(const DevPlan&, const T*, void*, hipStream_t);
+  template hipError_t launch_forward3d<T>(const DevPlan&, const T*, void*, hipStream_t); \
+  template hipError_t launch_cfft_x_inv_batch<T>(const BatchStage&, const BatchIO&, hipStream_t); \
+  template hipError_t launch_cfft_y_inv_batch<T>(const BatchStage&, const BatchIO&, hipStream_t); \
+  template hipError_t launch_c2r_z_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

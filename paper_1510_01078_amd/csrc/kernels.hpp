@@ -112,4 +112,72 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 template <typename T>
 hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Batched launches: one launch per stage serves up to kBatchMax problems of
+// different sizes. The work items of a stage are the blocks of every
+// problem, numbered problem after problem; prefix[p] is the first item of
+// problem p (prefix[nprob] = total). Each problem's arguments sit in a device
+// table; only the per-call input and output pointers travel in BatchIO (a
+// kernel argument), so a batched call allocates and synchronises nothing.
+// ---------------------------------------------------------------------------
+constexpr int kBatchMax = 64;
+
+struct BatchIO {
+  const void* in[kBatchMax];
+  void* out[kBatchMax];
+};
+
+struct FftView {
+  int n = 0, npass = 0;
+  const void* pass = nullptr;
+  const void* tw = nullptr;
+};
+
+struct TemporalBA {
+  const void* hw; const void* deap; FftView fd; int M, Nt, n0, b_lo, nb; void* Gt;
+};
+struct SpreadBA {
+  const void* Gt; const int* tile_off; const int* tile_sens; const int* sbx; const int* sby;
+  const void* swx; const void* swy; int nb, w, n_x, n_y, tiles_x, nchunks; void* U;
+};
+struct FftXBA {
+  const void* U; FftView fd; int n_y, Nx, rows, gx; void* V;
+};
+struct FftYBA {
+  const void* V; const void* dcx; const void* dcy; FftView fd; int nb, Nx, Ny, bins, gx; void* Gh;
+};
+struct GatherBA {
+  const void* Gh; const void* hcoef; int nb, b_lo, Nx, Ny, Nz, wt, deg;
+  double s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale; void* Fh;
+};
+struct CfftBA {
+  void* F; FftView fd; int Ny, Lh, lchunk, gx;  // Ny is used by the x pass only
+};
+struct C2rBA {
+  const void* F; FftView fd; long long nrows; int rows;
+};
+
+// One stage of a batched call: its argument table (one entry per problem),
+// prefix sums of work items, the dynamic LDS bytes (maximum over problems)
+// and the grid (0: one block per work item; otherwise blocks that loop over
+// the work items).
+struct BatchStage {
+  const void* args = nullptr;
+  const int* prefix = nullptr;
+  int nprob = 0;
+  int total = 0;
+  size_t lds = 0;
+  int grid = 0;
+  bool kahan = false;  // spread with compensated summation
+};
+
+template <typename T> hipError_t launch_temporal_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_spread_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_fft_x_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_fft_y_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_cfft_x_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_cfft_y_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+template <typename T> hipError_t launch_c2r_z_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
+
 }  // namespace patk

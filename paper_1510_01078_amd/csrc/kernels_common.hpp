@@ -4,6 +4,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "fft_device.hpp"
 #include "kernels.hpp"
 
@@ -49,9 +53,20 @@ __device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int 
 }
 
 // Allow a kernel more than the default dynamic LDS when a launch needs it.
+// The largest size granted per (kernel, device) is remembered, so repeated
+// launches (also inside a stream capture) make no runtime call.
 static inline hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> granted;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& have = granted[{fn, dev}];
+  if (bytes <= have) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e == hipSuccess) have = bytes;
+  return e;
 }
 
 template <typename T>
@@ -63,6 +78,41 @@ static inline FftDesc<T> as_desc(const FftRaw& r) {
   d.pass = static_cast<const FftPass*>(r.dpass);
   d.tw = static_cast<const cx<T>*>(r.tw);
   return d;
+}
+
+static inline FftView as_view(const FftRaw& r) {
+  FftView v;
+  v.n = r.n;
+  v.npass = r.npass;
+  v.pass = r.dpass;
+  v.tw = r.tw;
+  return v;
+}
+
+template <typename T>
+__host__ __device__ inline FftDesc<T> view_desc(const FftView& v) {
+  FftDesc<T> d;
+  d.n = v.n;
+  d.npass = v.npass;
+  d.pass = static_cast<const FftPass*>(v.pass);
+  d.tw = static_cast<const cx<T>*>(v.tw);
+  return d;
+}
+
+// Problem of batched work item w: the largest p with prefix[p] <= w.
+__device__ __forceinline__ int batch_locate(const int* __restrict__ prefix, int nprob, int w) {
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= w) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Grid of a batched launch: one block per work item, or `st.grid` blocks
+// striding over the items.
+static inline unsigned batch_grid(const BatchStage& st) {
+  return unsigned(st.grid > 0 && st.grid < st.total ? st.grid : st.total);
 }
 
 }  // namespace patk

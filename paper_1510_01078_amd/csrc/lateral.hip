@@ -13,15 +13,15 @@ namespace patk {
 // U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
-                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
+__device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
+                                           int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm, int bx, int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_x = fd.n;
   const int bstride = lseq(n_x);
-  const int b = b_begin + blockIdx.y;
-  const int py0 = blockIdx.x * rows;
+  const int b = b_begin + by;
+  const int py0 = bx * rows;
   const int nr = min(rows, n_y - py0);
   const cx<T>* src = U + (size_t(b - b_begin) * n_y + py0) * n_x;
   const FastDiv div_nx(n_x), div_nr(nr);
@@ -50,6 +50,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__
 }
 
 template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
+                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
+  fft_x_body<T>(U, n_y, Nx, rows, b_begin, fd, V, wm, blockIdx.x, blockIdx.y);
+}
+
+template <typename T>
 hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s) {
   const FftCfg cfg = fft_cfg();
   const int rows = fft_batch<T>(p.n_x, cfg.threads, cfg.cap);
@@ -71,16 +77,16 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
 // of each lateral mode are contiguous: V[b][jj][py] -> Gh[jj][kk][b].
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
-                                                     const T* __restrict__ dcx, const T* __restrict__ dcy,
-                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
+__device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
+                                           const T* __restrict__ dcx, const T* __restrict__ dcy,
+                                           FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm, int bx, int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_y = fd.n;
   const int bstride = lseq(n_y);
-  const int jj = blockIdx.y;
-  const int b0 = blockIdx.x * bins;
+  const int jj = by;
+  const int b0 = bx * bins;
   const int nbc = min(bins, nb - b0);
   const FastDiv div_ny(n_y), div_nbc(nbc);
   staged_copy<kFftMaxV>(
@@ -112,6 +118,13 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__
         const int kk = div_nbc(q);
         dst[size_t(kk) * nb + (q - kk * nbc)] = v;
       });
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
+                                                     const T* __restrict__ dcx, const T* __restrict__ dcy,
+                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
+  fft_y_body<T>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -260,11 +273,61 @@ hipError_t launch_fft_x_t(const DevPlan& p, const void* V, void* U, int b_begin,
   return hipGetLastError();
 }
 
+// Batched forms of the x and y passes.
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const FftXBA a = args[p];
+    const int local = w - prefix[p];
+    const int by = local / a.gx;
+    fft_x_body<T>(static_cast<const cx<T>*>(a.U), a.n_y, a.Nx, a.rows, 0, view_desc<T>(a.fd),
+                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const FftYBA a = args[p];
+    const int local = w - prefix[p];
+    const int by = local / a.gx;
+    fft_y_body<T>(static_cast<const cx<T>*>(a.V), a.nb, a.Nx, a.Ny, a.bins, static_cast<const T*>(a.dcx),
+                  static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, local - by * a.gx,
+                  by);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_fft_x_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_x_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const FftXBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fft_y_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fft_y_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const FftYBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
 #define PATK_INST(T)                                                                    \
   template hipError_t launch_fft_x<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
   template hipError_t launch_fft_y<T>(const DevPlan&, const void*, void*, hipStream_t);          \
   template hipError_t launch_fft_y_t<T>(const DevPlan&, const void*, void*, hipStream_t);        \
-  template hipError_t launch_fft_x_t<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);
+  template hipError_t launch_fft_x_t<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
+  template hipError_t launch_fft_x_batch<T>(const BatchStage&, const BatchIO&, hipStream_t); \
+  template hipError_t launch_fft_y_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -41,11 +41,11 @@ __device__ __forceinline__ void accum(cx<T>& a, cx<T>& c, T wt, cx<T> g) {
 }
 
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
-                                                const int* __restrict__ tile_sens, const int* __restrict__ sbx,
-                                                const int* __restrict__ sby, const T* __restrict__ swx,
-                                                const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
-                                                int nchunks, int b_begin, int b_end, cx<T>* __restrict__ U) {
+__device__ __forceinline__ void spread_body(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
+                                            const int* __restrict__ tile_sens, const int* __restrict__ sbx,
+                                            const int* __restrict__ sby, const T* __restrict__ swx,
+                                            const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
+                                            int nchunks, int b_begin, int b_end, cx<T>* __restrict__ U, int bx) {
   constexpr int BC = kSpreadBins;
   constexpr int SB = kSpreadBatch;
   __shared__ int s_bx[SB], s_by[SB];
@@ -54,8 +54,8 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   // bin groups vary fastest: groups running together share one tile's sensor
   // list and read whole per-sensor rows of Gt (measured faster on MI355X than
   // ordering by tile)
-  const int chunk = blockIdx.x % nchunks;
-  const int tile = blockIdx.x / nchunks;
+  const int chunk = bx % nchunks;
+  const int tile = bx / nchunks;
   const int tyi = tile / tiles_x;
   const int txi = tile - tyi * tiles_x;
   const int tid = threadIdx.x;
@@ -138,13 +138,24 @@ __global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, in
   }
 }
 
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(256) void k_spread(const cx<T>* __restrict__ Gt, int nb, const int* __restrict__ tile_off,
+                                                const int* __restrict__ tile_sens, const int* __restrict__ sbx,
+                                                const int* __restrict__ sby, const T* __restrict__ swx,
+                                                const T* __restrict__ swy, int w, int n_x, int n_y, int tiles_x,
+                                                int nchunks, int b_begin, int b_end, cx<T>* __restrict__ U) {
+  spread_body<T, KAHAN>(Gt, nb, tile_off, tile_sens, sbx, sby, swx, swy, w, n_x, n_y, tiles_x, nchunks, b_begin, b_end,
+                        U, blockIdx.x);
+}
+
 template <typename T>
 hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin, int b_end, hipStream_t s) {
   if (p.w_xy > kMaxW || b_begin < 0 || b_end > p.nb || b_begin >= b_end) return hipErrorInvalidValue;
   const int nchunks = (b_end - b_begin + kSpreadBins - 1) / kSpreadBins;
   const long long blocks = (long long)p.tiles_x * p.tiles_y * nchunks;
   if (p.kahan)
-    hipLaunchKernelGGL((k_spread<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt), p.nb,
+    hipLaunchKernelGGL((k_spread<T, true>), dim3((unsigned)blocks), dim3(256), 0, s, static_cast<const cx<T>*>(Gt),
+                       p.nb,
                        p.tile_off, p.tile_sens, p.sbx, p.sby, static_cast<const T*>(p.swx),
                        static_cast<const T*>(p.swy), p.w_xy, p.n_x, p.n_y, p.tiles_x, nchunks, b_begin, b_end,
                        static_cast<cx<T>*>(U));
@@ -156,7 +167,33 @@ hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin,
   return hipGetLastError();
 }
 
-#define PATK_INST(T) template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);
+// Batched form: one launch over the (tile, bin group) items of every problem.
+template <typename T, bool KAHAN>
+__global__ __launch_bounds__(256) void k_spread_batch(const SpreadBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const SpreadBA a = args[p];
+    spread_body<T, KAHAN>(static_cast<const cx<T>*>(a.Gt), a.nb, a.tile_off, a.tile_sens, a.sbx, a.sby,
+                          static_cast<const T*>(a.swx), static_cast<const T*>(a.swy), a.w, a.n_x, a.n_y, a.tiles_x,
+                          a.nchunks, 0, a.nb, static_cast<cx<T>*>(a.U), w - prefix[p]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_spread_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  if (st.kahan)
+    hipLaunchKernelGGL((k_spread_batch<T, true>), dim3(batch_grid(st)), dim3(256), 0, s,
+                       static_cast<const SpreadBA*>(st.args), st.prefix, st.nprob, st.total, io);
+  else
+    hipLaunchKernelGGL((k_spread_batch<T, false>), dim3(batch_grid(st)), dim3(256), 0, s,
+                       static_cast<const SpreadBA*>(st.args), st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
+#define PATK_INST(T) template hipError_t launch_spread<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
+  template hipError_t launch_spread_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -18,16 +18,16 @@ namespace patk {
 constexpr int kTemporalThreads = 512;
 
 template <typename T>
-__global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
-                                                             const T* __restrict__ hw, const T* __restrict__ deap,
-                                                             FftDesc<T> fd, int b_lo, int nb, int pairs,
-                                                             cx<T>* __restrict__ Gt) {
+__device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, int Nt, int n0,
+                                              const T* __restrict__ hw, const T* __restrict__ deap,
+                                              FftDesc<T> fd, int b_lo, int nb, int pairs,
+                                              cx<T>* __restrict__ Gt, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_t = fd.n;
   const int L = lseq(n_t);
-  const int mbase = 2 * pairs * blockIdx.x;  // first sensor of this group
+  const int mbase = 2 * pairs * bx;  // first sensor of this group
   const int np = min(pairs, (M - mbase + 1) / 2);
   for (int q = tid; q < np * L; q += nthr) buf[q] = cx<T>{T(0), T(0)};
   __syncthreads();
@@ -68,6 +68,14 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restri
     Gt[size_t(m0) * nb + i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
     if (m0 + 1 < M) Gt[size_t(m0 + 1) * nb + i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
+                                                             const T* __restrict__ hw, const T* __restrict__ deap,
+                                                             FftDesc<T> fd, int b_lo, int nb, int pairs,
+                                                             cx<T>* __restrict__ Gt) {
+  temporal_body<T>(g, M, Nt, n0, hw, deap, fd, b_lo, nb, pairs, Gt, blockIdx.x);
 }
 
 template <typename T>
@@ -147,9 +155,33 @@ hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t
   return hipGetLastError();
 }
 
+// Batched form: one launch over the sensor pairs of every problem.
+template <typename T>
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const TemporalBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    const int p = batch_locate(prefix, nprob, w);
+    const TemporalBA a = args[p];
+    temporal_body<T>(static_cast<const T*>(io.in[p]), a.M, a.Nt, a.n0, static_cast<const T*>(a.hw),
+                     static_cast<const T*>(a.deap), view_desc<T>(a.fd), a.b_lo, a.nb, 1, static_cast<cx<T>*>(a.Gt),
+                     w - prefix[p]);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_temporal_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
+  if (st.total <= 0) return hipSuccess;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_temporal_batch<T>), dim3(batch_grid(st)), dim3(kTemporalThreads), st.lds, s, static_cast<const TemporalBA*>(st.args),
+                     st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
+}
+
 #define PATK_INST(T)                                                                      \
   template hipError_t launch_temporal<T>(const DevPlan&, const T*, void*, bool, hipStream_t); \
-  template hipError_t launch_temporal_t<T>(const DevPlan&, const void*, T*, hipStream_t);
+  template hipError_t launch_temporal_t<T>(const DevPlan&, const void*, T*, hipStream_t); \
+  template hipError_t launch_temporal_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

@@ -18,6 +18,55 @@ _KERNELS = {"gaussian": N.PAT_KERNEL_GAUSSIAN, "kaiser_bessel": N.PAT_KERNEL_KAI
 _PRECISIONS = {"fp64": N.PAT_FP64, "fp32": N.PAT_FP32, "fp32_kahan": N.PAT_FP32_KAHAN}
 
 
+def build_desc(sensor_xy, n_t, dt, c, shape, extent, sensor_h=None, sigma_xy=2.0, width_xy=8, sigma_t=2.0,
+               width_t=8, kernel="kaiser_bessel", precision="fp32", temporal_interp="window"):
+    """A pat_plan_desc for one problem and the host arrays it points to
+    (keep them alive until the plan is built)."""
+    lib = N.load()
+    xy = np.ascontiguousarray(sensor_xy, dtype=np.float64).reshape(-1, 2)
+    h = None if sensor_h is None else np.ascontiguousarray(sensor_h, dtype=np.float64).reshape(-1)
+    if h is not None and h.shape[0] != xy.shape[0]:
+        raise ValueError("sensor_h must have one entry per sensor")
+    d = N.PlanDesc()
+    N.check(lib.pat_plan_desc_init(C.byref(d)), "pat_plan_desc_init")
+    d.n_sensors = xy.shape[0]
+    d.n_t = int(n_t)
+    d.dt = float(dt)
+    d.c = float(c)
+    d.sensor_xy = xy.ctypes.data_as(C.POINTER(C.c_double))
+    d.sensor_h = h.ctypes.data_as(C.POINTER(C.c_double)) if h is not None else None
+    d.nx, d.ny, d.nz = (int(v) for v in shape)
+    d.lx, d.ly, d.lz = (float(v) for v in extent)
+    d.sigma_xy = float(sigma_xy)
+    d.width_xy = int(width_xy)
+    d.sigma_t = float(sigma_t)
+    d.width_t = int(width_t)
+    d.kernel = _KERNELS[kernel]
+    d.precision = _PRECISIONS[precision]
+    d.temporal_interp = {"window": N.PAT_INTERP_WINDOW, "linear": N.PAT_INTERP_LINEAR}[temporal_interp]
+    return d, (xy, h)
+
+
+def torch_allocator(device, blocks):
+    """Allocator callbacks handing torch's caching allocator to the library:
+    each block is a uint8 tensor kept in `blocks` (keyed by address) until freed."""
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+            p = t.data_ptr()
+            blocks[p] = t
+            return p
+        except Exception:  # allocation failure -> NULL -> PAT_ERR_ALLOC
+            return None
+
+    def _free(ptr, ctx):
+        blocks.pop(ptr, None)
+
+    return N.ALLOC_FN(_alloc), N.FREE_FN(_free)
+
+
 class Plan:
     """A reconstruction plan for one sensor geometry, trace length and grid.
 
@@ -44,55 +93,21 @@ class Plan:
         self.precision = precision
         self.dtype = torch.float64 if precision == "fp64" else torch.float32
         self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
-        xy = np.ascontiguousarray(sensor_xy, dtype=np.float64).reshape(-1, 2)
-        self._xy = xy
-        self._h = None if sensor_h is None else np.ascontiguousarray(sensor_h, dtype=np.float64).reshape(-1)
-        if self._h is not None and self._h.shape[0] != xy.shape[0]:
-            raise ValueError("sensor_h must have one entry per sensor")
-        self.m = xy.shape[0]
+        self.m = int(np.asarray(sensor_xy).reshape(-1, 2).shape[0])
         self.n_t = int(n_t)
         self.shape = tuple(int(s) for s in shape)
         self.extent = tuple(float(e) for e in extent)
-
-        d = N.PlanDesc()
-        N.check(self._lib.pat_plan_desc_init(C.byref(d)), "pat_plan_desc_init")
-        d.n_sensors = self.m
-        d.n_t = self.n_t
-        d.dt = float(dt)
-        d.c = float(c)
-        d.sensor_xy = xy.ctypes.data_as(C.POINTER(C.c_double))
-        d.sensor_h = self._h.ctypes.data_as(C.POINTER(C.c_double)) if self._h is not None else None
-        d.nx, d.ny, d.nz = self.shape
-        d.lx, d.ly, d.lz = self.extent
-        d.sigma_xy = float(sigma_xy)
-        d.width_xy = int(width_xy)
-        d.sigma_t = float(sigma_t)
-        d.width_t = int(width_t)
-        d.kernel = _KERNELS[kernel]
-        d.precision = _PRECISIONS[precision]
-        d.temporal_interp = {"window": N.PAT_INTERP_WINDOW, "linear": N.PAT_INTERP_LINEAR}[temporal_interp]
+        d, keep = build_desc(sensor_xy, n_t, dt, c, shape, extent, sensor_h, sigma_xy, width_xy, sigma_t, width_t,
+                             kernel, precision, temporal_interp)
+        self._xy, self._h = keep
 
         self._blocks = {}
-        dev = self.device
-
-        def _alloc(nbytes, ctx):
-            try:
-                t = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
-                p = t.data_ptr()
-                self._blocks[p] = t
-                return p
-            except Exception:  # allocation failure -> NULL -> PAT_ERR_ALLOC
-                return None
-
-        def _free(ptr, ctx):
-            self._blocks.pop(ptr, None)
-
-        self._alloc_cb = N.ALLOC_FN(_alloc)
-        self._free_cb = N.FREE_FN(_free)
+        self._alloc_cb, self._free_cb = torch_allocator(self.device, self._blocks)
         d.alloc = self._alloc_cb
         d.free = self._free_cb
         self._desc = d
         handle = C.c_void_p()
+        dev = self.device
         with torch.cuda.device(dev):
             stream = torch.cuda.current_stream(dev)
             N.check(self._lib.nufft_plan(C.byref(d), C.c_void_p(stream.cuda_stream), C.byref(handle)), "nufft_plan")
