@@ -70,6 +70,64 @@ def stage_bytes(plan, p, eb):
     ]
 
 
+def _time_calls(fn, steps, warmup, dev):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize(dev)
+    return 1000.0 * (time.perf_counter() - t0) / steps
+
+
+def bench_batch(args, dev):
+    """32 uneven problems (Ns ~ U{24..96}, Nt ~ U{512..2048}, 64^3..192^3):
+    one batched call (eight launches), the same call replayed from a HIP
+    graph, and the 32 problems one plan after another."""
+    import torch
+    from paper_1510_01078_amd import Plan, inputs
+    from paper_1510_01078_amd.batch import Batch, problem_dict
+    probs = inputs.batched_problems(32, seed=1003)
+    settings = dict(kernel=args.kernel, sigma_xy=args.sigma_xy, width_xy=args.width_xy, sigma_t=args.sigma_t,
+                    width_t=args.width_t)
+    log("batch: building 32 plans (cache-sized groups, then the default single group)")
+    one = Batch([problem_dict(p) for p in probs], precision=args.precision, defaults=settings, device=dev,
+                group_bytes=160 << 20)
+    dtype = one.dtype
+    gs = [torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, dtype) for p in probs]
+    outs = [torch.empty(s, dtype=dtype, device=dev) for s in one.shapes]
+    ms_one = _time_calls(lambda: one.reconstruct(gs, outs), args.steps, args.warmup, dev)
+    one.close()
+    b = Batch([problem_dict(p) for p in probs], precision=args.precision, defaults=settings, device=dev)
+    ms_batch = _time_calls(lambda: b.reconstruct(gs, outs), args.steps, args.warmup, dev)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.reconstruct(gs, outs)
+    ms_graph = _time_calls(graph.replay, args.steps, args.warmup, dev)
+    groups = b.groups
+    b.close()
+    del graph
+    plans = [Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision=args.precision, device=dev,
+                  **settings) for p in probs]
+
+    def sequential():
+        for pl, g, o in zip(plans, gs, outs):
+            pl.reconstruct(g, out=o)
+    ms_seq = _time_calls(sequential, args.steps, args.warmup, dev)
+    for pl in plans:
+        pl.close()
+    voxels = float(sum(np.prod(p.shape) for p in probs))
+    log(f"batch: {ms_batch:.3f} ms batched ({groups} groups), {ms_graph:.3f} ms graph replay, "
+        f"{ms_one:.3f} ms in 160 MiB cache-sized groups, {ms_seq:.3f} ms sequential")
+    return {"problems": len(probs), "voxels": int(voxels), "groups": groups, "ms_per_batch": round(ms_batch, 4),
+            "ms_per_batch_cache_groups": round(ms_one, 4),
+            "ms_per_batch_graph": round(ms_graph, 4), "ms_sequential_plans": round(ms_seq, 4),
+            "voxels_per_s": voxels / (ms_batch * 1e-3), "voxels_per_s_graph": voxels / (ms_graph * 1e-3),
+            "speedup_vs_sequential": round(ms_seq / ms_batch, 3)}
+
+
 def recorded_traffic(args, band_bins):
     """HBM bytes per spread launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when no record matches this workload or the spread
@@ -160,6 +218,8 @@ def main():
     ap.add_argument("--width-t", type=int, default=10)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-sample", type=int, default=8, help="lateral x-modes in the oracle sample")
+    ap.add_argument("--batch", choices=["on", "off"], default="on",
+                    help="also time the 32-problem batched reconstruction against sequential plans")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of one plain device-to-device copy run before the timed loop (scales HBM counters)")
     args = ap.parse_args()
@@ -272,6 +332,9 @@ def main():
                      "stages_ms": {n: round(v / max(1, nc), 5) for n, v in zip(snames, sm)}}
         log(f"{name}: {ops[name]['ms_per_call']:.4f} ms per call")
     result["operators"] = ops
+
+    if args.batch == "on":
+        result["batch"] = bench_batch(args, dev)
 
     if args.cpu_baseline == "on":
         log("gpu spectrum for the sample check")

@@ -210,28 +210,41 @@ pat_status pat_forward_dxy(pat_plan* plan, const void* f, int32_t axis, void* g,
  * problems, so small problems share the device instead of running one after
  * another. Results equal pat_reconstruct's for each problem bit for bit.
  *
+ * Problems are run in groups of at most 32 (one group per 32 problems by
+ * default). With group_bytes > 0 a group also takes problems, sorted by the
+ * size of their oversampled lateral grid, only while their grids together
+ * stay within group_bytes (meant for handing each stage's output to the next
+ * through the last-level cache; on MI355X this measured slower than one
+ * group, so 0, no budget, is the default). Groups run one after another
+ * (eight launches each) and share one workspace (the largest group's).
+ *
  * pat_batch_create builds one plan per descriptor (as nufft_plan), uploads
- * per-problem argument tables and allocates the batch's workspace through
- * descs[0]'s allocator (or hipMalloc), then synchronises `stream`. The batch
- * owns its plans, tables and workspace, so calls on one batch must not
- * overlap in time (they share the workspace).
+ * per-group argument tables and allocates the workspace through descs[0]'s
+ * allocator (or hipMalloc), then synchronises `stream`. The batch owns its
+ * plans, tables and workspace, so calls on one batch must not overlap in
+ * time (they share the workspace).
  * ------------------------------------------------------------------------ */
 typedef struct pat_batch pat_batch;
 
-pat_status pat_batch_create(const pat_plan_desc* descs, int32_t count, void* stream, pat_batch** out);
+pat_status pat_batch_create(const pat_plan_desc* descs, int32_t count, size_t group_bytes, void* stream,
+                            pat_batch** out);
+
+/* Number of problem groups the batch runs (each: eight launches). */
+pat_status pat_batch_groups(const pat_batch* batch, int32_t* groups);
 
 /* Plan of problem `index` (read-only, e.g. for pat_plan_get_info). */
 pat_status pat_batch_get_plan(const pat_batch* batch, int32_t index, const pat_plan** plan);
 
-/* Grid of the batched launches: 0 (default) launches one work-group per work
- * item; blocks > 0 launches at most that many work-groups, each looping over
- * the work items (a persistent launch). Results do not depend on it. */
+/* Grid of the batched launches: blocks > 0 (default 16384) launches at most
+ * that many work-groups, each loading the group's arguments into LDS once and
+ * looping over the work items (a persistent launch); 0 launches one
+ * work-group per work item. Results do not depend on it. */
 pat_status pat_batch_set_grid(pat_batch* batch, int32_t blocks);
 
 /* f[p] = R g[p] for every problem p: g and f are HOST arrays of `count`
  * DEVICE pointers with the layouts of pat_reconstruct. Enqueues eight kernels
- * on `stream` (no allocation, no synchronisation), so the call can be
- * captured into a HIP graph. Inputs and outputs must not overlap. */
+ * per group on `stream` (no allocation, no synchronisation), so the call can
+ * be captured into a HIP graph. Inputs and outputs must not overlap. */
 pat_status pat_batch_reconstruct(pat_batch* batch, const void* const* g, void* const* f, void* stream);
 
 /* Synchronises the device, then releases the batch. NULL is ignored. */

@@ -85,7 +85,8 @@ SIGNATURES = {
     "pat_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_forward_dxy": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "pat_batch_create": (C.c_int, [C.POINTER(PlanDesc), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pat_batch_create": (C.c_int, [C.POINTER(PlanDesc), C.c_int32, C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "pat_batch_groups": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "pat_batch_get_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p)]),
     "pat_batch_set_grid": (C.c_int, [C.c_void_p, C.c_int32]),
     "pat_batch_reconstruct": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),

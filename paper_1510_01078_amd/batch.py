@@ -18,9 +18,11 @@ class Batch:
     """problems: sequence of dicts with keys sensor_xy, n_t, dt, c, shape,
     extent and optionally sensor_h and the window settings (sigma_xy,
     width_xy, sigma_t, width_t, kernel, temporal_interp); `defaults` fills
-    settings a problem leaves out. precision applies to the whole batch."""
+    settings a problem leaves out. precision applies to the whole batch;
+    group_bytes is the cache budget of a group of problems (0: the
+    library's default; a huge value: one group)."""
 
-    def __init__(self, problems, precision="fp32", device=None, defaults=None):
+    def __init__(self, problems, precision="fp32", device=None, defaults=None, group_bytes=0):
         import torch
 
         self._torch = torch
@@ -52,10 +54,13 @@ class Batch:
         handle = C.c_void_p()
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device)
-            N.check(self._lib.pat_batch_create(descs, len(problems), C.c_void_p(stream.cuda_stream),
-                                               C.byref(handle)), "pat_batch_create")
+            N.check(self._lib.pat_batch_create(descs, len(problems), int(group_bytes),
+                                               C.c_void_p(stream.cuda_stream), C.byref(handle)), "pat_batch_create")
         self._handle = handle
         self.count = len(problems)
+        ng = C.c_int32()
+        N.check(self._lib.pat_batch_groups(handle, C.byref(ng)), "pat_batch_groups")
+        self.groups = ng.value
         self.info = []
         for i in range(self.count):
             plan = C.c_void_p()

@@ -255,13 +255,16 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
 
 // Batched form of the reconstruction's interpolation (image-ready spectrum).
 template <typename T>
-__global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict__ args, const int* __restrict__ prefix,
+                             int nprob, int total, BatchIO io) {
+  __shared__ BatchMeta<GatherBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const GatherBA a = args[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const GatherBA a = batch_args(meta, p);
     gather_body<T, MODE_IMAGE>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k, a.kxu, a.kyu,
                                a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg, static_cast<const T*>(a.hcoef),
-                               static_cast<cx<T>*>(a.Fh), w - prefix[p]);
+                               static_cast<cx<T>*>(a.Fh), w - meta.prefix[p]);
     __syncthreads();
   }
 }
@@ -271,8 +274,8 @@ hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStrea
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gather_batch<T>), dim3(batch_grid(st)), dim3(256), st.lds, s, static_cast<const GatherBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_gather_batch<T>), dim3(batch_grid(st)), dim3(256), st.lds, s,
+                     static_cast<const GatherBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 

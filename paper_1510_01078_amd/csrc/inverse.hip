@@ -230,11 +230,15 @@ hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t 
 
 // Batched forms of the inverse passes.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_cfft_x_inv_batch(const CfftBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_cfft_x_inv_batch(const CfftBA* __restrict__ args,
+                                                                  const int* __restrict__ prefix, int nprob, int total,
+                                                                  BatchIO io) {
+  __shared__ BatchMeta<CfftBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const CfftBA a = args[p];
-    const int local = w - prefix[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const CfftBA a = batch_args(meta, p);
+    const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     cfft_x_body<T, true>(static_cast<cx<T>*>(a.F), a.Ny, a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
     __syncthreads();
@@ -242,11 +246,15 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_x_inv_batch(const CfftBA* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* __restrict__ args,
+                                                                  const int* __restrict__ prefix, int nprob, int total,
+                                                                  BatchIO io) {
+  __shared__ BatchMeta<CfftBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const CfftBA a = args[p];
-    const int local = w - prefix[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const CfftBA a = batch_args(meta, p);
+    const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     cfft_y_body<T, true>(static_cast<cx<T>*>(a.F), a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
     __syncthreads();
@@ -254,12 +262,16 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __restrict__ args,
+                                                             const int* __restrict__ prefix, int nprob, int total,
+                                                             BatchIO io) {
+  __shared__ BatchMeta<C2rBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const C2rBA a = args[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const C2rBA a = batch_args(meta, p);
     c2r_z_body<T>(static_cast<const cx<T>*>(a.F), a.nrows, a.rows, view_desc<T>(a.fd), static_cast<T*>(io.out[p]), 0,
-                  w - prefix[p]);
+                  w - meta.prefix[p]);
     __syncthreads();
   }
 }
@@ -269,8 +281,8 @@ hipError_t launch_cfft_x_inv_batch(const BatchStage& st, const BatchIO& io, hipS
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_x_inv_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cfft_x_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const CfftBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_cfft_x_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
+                     static_cast<const CfftBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 
@@ -279,8 +291,8 @@ hipError_t launch_cfft_y_inv_batch(const BatchStage& st, const BatchIO& io, hipS
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_y_inv_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cfft_y_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const CfftBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_cfft_y_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
+                     static_cast<const CfftBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 
@@ -289,8 +301,8 @@ hipError_t launch_c2r_z_batch(const BatchStage& st, const BatchIO& io, hipStream
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_c2r_z_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const C2rBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_c2r_z_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
+                     static_cast<const C2rBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 

@@ -121,16 +121,17 @@ hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t
 // kernel argument), so a batched call allocates and synchronises nothing.
 // ---------------------------------------------------------------------------
 constexpr int kBatchMax = 64;
+constexpr int kGroupMax = 32;  // problems per batched launch
 
 struct BatchIO {
-  const void* in[kBatchMax];
-  void* out[kBatchMax];
+  const void* in[kGroupMax];
+  void* out[kGroupMax];
 };
 
-struct FftView {
-  int n = 0, npass = 0;
-  const void* pass = nullptr;
-  const void* tw = nullptr;
+struct FftView {  // plain data (it also lives in LDS)
+  int n, npass;
+  const void* pass;
+  const void* tw;
 };
 
 struct TemporalBA {

@@ -99,8 +99,40 @@ __host__ __device__ inline FftDesc<T> view_desc(const FftView& v) {
   return d;
 }
 
+// A batched launch's per-problem arguments and work-item prefix sums, copied
+// into LDS once per work-group; each work item then finds its problem with
+// an LDS search and takes the arguments into scalar registers (as kernel
+// arguments would be), so no work item waits on dependent global loads.
+template <class A>
+struct BatchMeta {
+  int prefix[kGroupMax + 1];
+  A args[kGroupMax];
+};
+
+template <class A>
+__device__ __forceinline__ void batch_meta_load(BatchMeta<A>& m, const A* __restrict__ args,
+                                                const int* __restrict__ prefix, int nprob) {
+  static_assert(sizeof(A) % 4 == 0, "argument words");
+  const int nw = nprob * int(sizeof(A) / 4);
+  const int* src = reinterpret_cast<const int*>(args);
+  int* dst = reinterpret_cast<int*>(m.args);
+  for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i <= nprob; i += blockDim.x) m.prefix[i] = prefix[i];
+  __syncthreads();
+}
+
+template <class A>
+__device__ __forceinline__ A batch_args(const BatchMeta<A>& m, int p) {
+  A a;
+  const int* src = reinterpret_cast<const int*>(&m.args[p]);
+  int* dst = reinterpret_cast<int*>(&a);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(A) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return a;
+}
+
 // Problem of batched work item w: the largest p with prefix[p] <= w.
-__device__ __forceinline__ int batch_locate(const int* __restrict__ prefix, int nprob, int w) {
+__device__ __forceinline__ int batch_locate(const int* prefix, int nprob, int w) {
   int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;

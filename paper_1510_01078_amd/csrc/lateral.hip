@@ -275,11 +275,15 @@ hipError_t launch_fft_x_t(const DevPlan& p, const void* V, void* U, int b_begin,
 
 // Batched forms of the x and y passes.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __restrict__ args,
+                                                             const int* __restrict__ prefix, int nprob, int total,
+                                                             BatchIO io) {
+  __shared__ BatchMeta<FftXBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const FftXBA a = args[p];
-    const int local = w - prefix[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const FftXBA a = batch_args(meta, p);
+    const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     fft_x_body<T>(static_cast<const cx<T>*>(a.U), a.n_y, a.Nx, a.rows, 0, view_desc<T>(a.fd),
                   static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by);
@@ -288,11 +292,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __res
 }
 
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __restrict__ args,
+                                                             const int* __restrict__ prefix, int nprob, int total,
+                                                             BatchIO io) {
+  __shared__ BatchMeta<FftYBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const FftYBA a = args[p];
-    const int local = w - prefix[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const FftYBA a = batch_args(meta, p);
+    const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     fft_y_body<T>(static_cast<const cx<T>*>(a.V), a.nb, a.Nx, a.Ny, a.bins, static_cast<const T*>(a.dcx),
                   static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, local - by * a.gx,
@@ -306,8 +314,8 @@ hipError_t launch_fft_x_batch(const BatchStage& st, const BatchIO& io, hipStream
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fft_x_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const FftXBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_fft_x_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
+                     static_cast<const FftXBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 
@@ -316,8 +324,8 @@ hipError_t launch_fft_y_batch(const BatchStage& st, const BatchIO& io, hipStream
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fft_y_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s, static_cast<const FftYBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_fft_y_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
+                     static_cast<const FftYBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 

@@ -169,13 +169,16 @@ hipError_t launch_spread(const DevPlan& p, const void* Gt, void* U, int b_begin,
 
 // Batched form: one launch over the (tile, bin group) items of every problem.
 template <typename T, bool KAHAN>
-__global__ __launch_bounds__(256) void k_spread_batch(const SpreadBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(256) void k_spread_batch(const SpreadBA* __restrict__ args, const int* __restrict__ prefix,
+                             int nprob, int total, BatchIO io) {
+  __shared__ BatchMeta<SpreadBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const SpreadBA a = args[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const SpreadBA a = batch_args(meta, p);
     spread_body<T, KAHAN>(static_cast<const cx<T>*>(a.Gt), a.nb, a.tile_off, a.tile_sens, a.sbx, a.sby,
                           static_cast<const T*>(a.swx), static_cast<const T*>(a.swy), a.w, a.n_x, a.n_y, a.tiles_x,
-                          a.nchunks, 0, a.nb, static_cast<cx<T>*>(a.U), w - prefix[p]);
+                          a.nchunks, 0, a.nb, static_cast<cx<T>*>(a.U), w - meta.prefix[p]);
     __syncthreads();
   }
 }

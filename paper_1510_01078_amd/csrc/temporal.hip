@@ -157,13 +157,17 @@ hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t
 
 // Batched form: one launch over the sensor pairs of every problem.
 template <typename T>
-__global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const TemporalBA* __restrict__ args, const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const TemporalBA* __restrict__ args,
+                                                                     const int* __restrict__ prefix, int nprob, int total,
+                                                                     BatchIO io) {
+  __shared__ BatchMeta<TemporalBA> meta;
+  batch_meta_load(meta, args, prefix, nprob);
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = batch_locate(prefix, nprob, w);
-    const TemporalBA a = args[p];
+    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
+    const TemporalBA a = batch_args(meta, p);
     temporal_body<T>(static_cast<const T*>(io.in[p]), a.M, a.Nt, a.n0, static_cast<const T*>(a.hw),
                      static_cast<const T*>(a.deap), view_desc<T>(a.fd), a.b_lo, a.nb, 1, static_cast<cx<T>*>(a.Gt),
-                     w - prefix[p]);
+                     w - meta.prefix[p]);
     __syncthreads();
   }
 }
@@ -173,8 +177,8 @@ hipError_t launch_temporal_batch(const BatchStage& st, const BatchIO& io, hipStr
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal_batch<T>), st.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_temporal_batch<T>), dim3(batch_grid(st)), dim3(kTemporalThreads), st.lds, s, static_cast<const TemporalBA*>(st.args),
-                     st.prefix, st.nprob, st.total, io);
+  hipLaunchKernelGGL((k_temporal_batch<T>), dim3(batch_grid(st)), dim3(kTemporalThreads), st.lds, s,
+                     static_cast<const TemporalBA*>(st.args), st.prefix, st.nprob, st.total, io);
   return hipGetLastError();
 }
 

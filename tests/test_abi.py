@@ -126,7 +126,9 @@ def test_null_arguments():
     assert lib.pat_forward_dxy(None, None, 0, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_forward_dxy(None, None, 2, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     h = C.c_void_p(99)
-    assert lib.pat_batch_create(None, 1, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT and h.value is None
+    assert lib.pat_batch_create(None, 1, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT and h.value is None
+    n = C.c_int32()
+    assert lib.pat_batch_groups(None, C.byref(n)) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_batch_reconstruct(None, None, None, None) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_batch_set_grid(None, 0) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_batch_get_plan(None, 0, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
@@ -138,8 +140,8 @@ def test_batch_count_and_precision_mix_rejected():
     xy = np.zeros((4, 2))
     descs = (N.PlanDesc * 2)(_desc(xy), _desc(xy, precision=N.PAT_FP64))
     h = C.c_void_p()
-    assert lib.pat_batch_create(descs, 2, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
-    assert lib.pat_batch_create(descs, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
-    assert lib.pat_batch_create(descs, 65, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_batch_create(descs, 2, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_batch_create(descs, 0, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_batch_create(descs, 65, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_timing_begin(None, 4) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_plan_desc_init(None) == N.PAT_ERR_INVALID_ARGUMENT

@@ -6,8 +6,8 @@ one launch per stage.
   bit (same kernels, same summation order), so the batch inherits the
   single-problem parity; the two smallest problems are also checked against
   the FP64 oracle (1e-5 relative L2, the FP32 target).
-* A persistent grid (work-groups looping over the work items) gives the
-  same bits.
+* The persistent grid (work-groups looping over the work items), smaller
+  or absent, gives the same bits.
 * The call captured in a HIP graph (torch.cuda.CUDAGraph) and replayed with
   new inputs, with eager work between replays, matches the eager call on
   every replay.
@@ -78,14 +78,19 @@ def test_batch_smallest_vs_oracle(batch_setup):
         assert e <= 1e-5
 
 
-def test_batch_persistent_grid_same_bits(batch_setup):
+def test_batch_grid_shapes_same_bits(batch_setup):
+    """Default persistent grid, a small persistent grid and one work-group
+    per work item give the same bits."""
     probs, b, gs = batch_setup
     a = [o.clone() for o in b.reconstruct(gs)]
-    b.set_grid(1024)
-    c = b.reconstruct(gs)
+    results = []
+    for blocks in (1024, 0):
+        b.set_grid(blocks)
+        results.append([o.clone() for o in b.reconstruct(gs)])
     torch.cuda.synchronize()
-    b.set_grid(0)
-    assert all(torch.equal(x, y) for x, y in zip(a, c))
+    b.set_grid(16384)
+    for c in results:
+        assert all(torch.equal(x, y) for x, y in zip(a, c))
 
 
 def test_batch_graph_replays(batch_setup):
