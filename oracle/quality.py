@@ -59,3 +59,24 @@ def rel_l2(a, b) -> float:
     a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
     b = np.asarray(b, dtype=a.dtype)
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def cylinder_roi(shape, extent, centre, diameter, height_ratio=8.0 / 9.0):
+    """Voxels inside the region of interest of Section 6.3: a cylinder with
+    its axis along z, the given diameter and height = height_ratio *
+    diameter (8:9), centred at centre = (x, y, z) metres. Voxel centres are
+    x_a = (a - Nx/2)X/Nx, y_b = (b - Ny/2)Y/Ny, z_e = e Z/Nz."""
+    nx, ny, nz = shape
+    X, Y, Z = extent
+    x = (np.arange(nx) - nx // 2) * (X / nx)
+    y = (np.arange(ny) - ny // 2) * (Y / ny)
+    z = np.arange(nz) * (Z / nz)
+    rad2 = (x[:, None, None] - centre[0]) ** 2 + (y[None, :, None] - centre[1]) ** 2
+    half = 0.5 * height_ratio * diameter
+    return (rad2 <= (0.5 * diameter) ** 2) & (np.abs(z[None, None, :] - centre[2]) <= half)
+
+
+def roi_box(mask):
+    """Index slices of the bounding box of a boolean mask."""
+    idx = np.nonzero(mask)
+    return tuple(slice(int(i.min()), int(i.max()) + 1) for i in idx)

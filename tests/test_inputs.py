@@ -1,5 +1,6 @@
 """Synthetic input generators: layouts, weights and the ball signal."""
 import numpy as np
+import pytest
 
 from paper_1510_01078_amd import inputs
 
@@ -93,3 +94,54 @@ def test_smooth235():
     assert inputs.smooth235(512) == 512
     assert inputs.smooth235(7) == 8
     assert inputs.smooth235(11) == 12
+
+
+# ----------------------------------------------------------------------------
+# equi-steradian placement (Appendix A) and the r^3 weights (Section 6.2)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,r0,drd", [(360, 8e-3, 16e-3), (870, 6e-3, 18e-3), (100, 10e-3, 8e-3)])
+def test_equi_steradian_rings_follow_the_slice_recursion(n, r0, drd):
+    """Rings hold 1 (the pole), then powers of two non-decreasing outward;
+    rebuilding the slice boundaries from the ring counts with
+    cos(th_k) = cos(th_{k-1}) - omega j_k/(2 pi), cos(th_1) = 1 - omega/(2 pi),
+    omega = 2 pi (1 - cos th_max)/n, puts every ring at the projected
+    mid-angle of its slice exactly (the last slice is cut at th_max)."""
+    import math
+    xy, r = inputs.equi_steradian_sensors(n, r0, drd)
+    rho = np.hypot(xy[:, 0], xy[:, 1])
+    radii, counts = np.unique(np.round(rho, 12), return_counts=True)
+    assert counts[0] == 1 and radii[0] == 0.0
+    assert all(c & (c - 1) == 0 for c in counts[1:])
+    assert all(a <= b for a, b in zip(counts[1:], counts[2:]))
+    assert np.all(rho < 0.5 * drd)
+    assert n <= len(xy) <= 1.25 * n
+    th_max = math.atan2(0.5 * drd, r0)
+    omega = 2 * math.pi * (1 - math.cos(th_max)) / n
+    cos_prev = 1 - omega / (2 * math.pi)
+    for rad, j in zip(radii[1:], counts[1:]):
+        cos_next = max(cos_prev - omega * j / (2 * math.pi), math.cos(th_max))
+        th_mid = 0.5 * (math.acos(cos_prev) + math.acos(cos_next))
+        assert abs(r0 * math.tan(th_mid) - rad) <= 1e-12 + 1e-9 * rad
+        cos_prev = cos_next
+
+
+def test_equi_steradian_local_equidistance():
+    """Seen from the centre of interest, nearest-neighbour angular spacings
+    vary little (the aim of the power-of-two doubling rule)."""
+    xy, _ = inputs.equi_steradian_sensors(360, 8e-3, 16e-3)
+    v = np.stack([xy[:, 0], xy[:, 1], -np.full(len(xy), 8e-3)], 1)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    ang = np.arccos(np.clip(v @ v.T, -1, 1))
+    np.fill_diagonal(ang, np.inf)
+    nn = ang.min(1)
+    assert nn.std() / nn.mean() < 0.15 and nn.max() / nn.min() < 1.6
+
+
+def test_r_cubed_weights():
+    xy, r = inputs.equi_steradian_sensors(360, 8e-3, 16e-3)
+    area = np.pi * 8e-3 ** 2
+    h = inputs.power_weights(xy, r, 3.0, area)
+    ratio = h / r ** 3
+    assert np.ptp(ratio) <= 1e-12 * ratio.mean()
+    assert abs(h.sum() - area) <= 1e-15 * area * len(h)

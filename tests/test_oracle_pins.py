@@ -281,3 +281,19 @@ def test_ball_physics_tiny_workload():
     truth = inputs.voxelise_balls(p.balls, nx, ny, nz, X, Y, Z)
     rho = quality.corrcoef(f, truth)
     assert rho > gold["corrcoef_min"]
+
+
+def test_cylinder_roi_volume_and_proportions():
+    """The ROI mask holds the cylinder's volume (pi r^2 h, h = 8/9 d) to the
+    voxel discretisation and its bounding box has the 8:9 proportions."""
+    from oracle.quality import cylinder_roi, roi_box
+    shape, ext = (128, 128, 128), (20e-3, 20e-3, 20e-3)
+    d = 9e-3
+    m = cylinder_roi(shape, ext, (0.0, 0.0, 7e-3), d)
+    dv = (20e-3 / 128) ** 3
+    vol = np.pi * (d / 2) ** 2 * (8 / 9 * d)
+    assert abs(m.sum() * dv - vol) <= 0.03 * vol
+    box = roi_box(m)
+    w = (box[0].stop - box[0].start) * 20e-3 / 128
+    h = (box[2].stop - box[2].start) * 20e-3 / 128
+    assert abs(h / w - 8 / 9) <= 0.04
