@@ -282,7 +282,8 @@ def main():
     spread_bytes_launch = sb[1] / rounds
     achieved = spread_bytes_launch / (spread_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args, plan.info["band_bins"]), "kernel": "k_spread",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args, plan.info["band_bins"]),
+                "kernel": "k_spread_wave",
                 "bytes_per_launch": int(spread_bytes_launch), "ms_per_launch": round(spread_ms, 5),
                 "launches_per_step": rounds}
 

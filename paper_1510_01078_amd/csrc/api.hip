@@ -250,6 +250,34 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   P->spread_pairs = (int64_t)inc.size();
   const size_t o_toff = blob.add(cnt.data(), cnt.size() * sizeof(int));
   const size_t o_tsens = blob.add(sens.data(), std::max<size_t>(1, sens.size()) * sizeof(int));
+  // wave-patch lists: sensors whose footprint meets each 16 x kPatchRows patch
+  // (a tile column and a group of rows), ascending per patch
+  const int PR = patk::kPatchRows;
+  dp.patches_y = (dp.n_y + PR - 1) / PR;
+  const int npatch = dp.tiles_x * dp.patches_y;
+  std::vector<int> pcnt(npatch + 1, 0);
+  std::vector<std::pair<int, int>> pinc;
+  pinc.reserve(size_t(M) * 6);
+  for (int m = 0; m < M; ++m) {
+    int txs[4], rgs[8], ntx = 0, nrg = 0;
+    for (int t = 0; t < w; ++t) {
+      const int tx = ((sbx[m] + t) % dp.n_x) / TS;
+      if (ntx < 4 && std::find(txs, txs + ntx, tx) == txs + ntx) txs[ntx++] = tx;
+      const int rg = ((sby[m] + t) % dp.n_y) / PR;
+      if (nrg < 8 && std::find(rgs, rgs + nrg, rg) == rgs + nrg) rgs[nrg++] = rg;
+    }
+    for (int a = 0; a < ntx; ++a)
+      for (int b = 0; b < nrg; ++b) pinc.emplace_back(rgs[b] * dp.tiles_x + txs[a], m);
+  }
+  for (auto& e : pinc) pcnt[e.first + 1]++;
+  for (int i = 0; i < npatch; ++i) pcnt[i + 1] += pcnt[i];
+  std::vector<int> psens(pinc.size());
+  {
+    std::vector<int> pos(pcnt.begin(), pcnt.end() - 1);
+    for (auto& e : pinc) psens[pos[e.first]++] = e.second;  // stable: sensors ascending per patch
+  }
+  const size_t o_poff = blob.add(pcnt.data(), pcnt.size() * sizeof(int));
+  const size_t o_psens = blob.add(psens.data(), std::max<size_t>(1, psens.size()) * sizeof(int));
   // home lists for the interpolation to the sensors: each sensor once, in
   // the tile holding its footprint origin, sensors ascending per tile
   std::vector<int> hcnt(ntiles + 1, 0), home(M);
@@ -316,6 +344,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.swy = at(o_swy);
   dp.tile_off = static_cast<const int*>(at(o_toff));
   dp.tile_sens = static_cast<const int*>(at(o_tsens));
+  dp.patch_off = static_cast<const int*>(at(o_poff));
+  dp.patch_sens = static_cast<const int*>(at(o_psens));
   dp.home_off = static_cast<const int*>(at(o_hoff));
   dp.home_sens = static_cast<const int*>(at(o_hsens));
   dp.dcx = at(o_dcx);

@@ -53,6 +53,9 @@ struct DevPlan {
   const void* swy = nullptr;      // [M][w]
   const int* tile_off = nullptr;  // [tiles+1]
   const int* tile_sens = nullptr; // sensors whose footprint meets each tile
+  const int* patch_off = nullptr; // [tiles_x*patches_y+1] sensors meeting each 16 x kPatchRows patch (CSR)
+  const int* patch_sens = nullptr;
+  int patches_y = 0;
   const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
   const int* home_sens = nullptr; // [M]
   const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
@@ -62,6 +65,7 @@ struct DevPlan {
 };
 
 constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
+constexpr int kPatchRows = 4;    // rows of the spread's one-wave patch (16 x 4 grid points)
 
 // Stage launchers; T = float or double. Buffers are device pointers.
 //
