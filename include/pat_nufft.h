@@ -100,7 +100,9 @@ typedef struct pat_plan_desc {
   double lx, ly, lz;         /* extents X, Y, Z in metres, > 0 */
   double sigma_xy;           /* lateral oversampling factor, >= 1.1 (grid = smooth(sigma*N)) */
   int32_t width_xy;          /* lateral window footprint w in grid points, even, 2..16 */
-  double sigma_t;            /* temporal oversampling factor, >= 1.1 (>= 1.0 for PAT_INTERP_LINEAR) */
+  double sigma_t;            /* temporal oversampling factor, >= 1.1 (>= 1.0 for PAT_INTERP_LINEAR); a
+                                minimum: short traces get a longer FFT when the band of bins the
+                                interpolation reads needs it (see pat_plan_info.nt_over) */
   int32_t width_t;           /* temporal window footprint, even, 2..16 */
   pat_kernel kernel;
   pat_precision precision;
@@ -129,6 +131,8 @@ typedef struct pat_plan_info {
   size_t table_bytes;        /* device bytes owned by the plan */
   int32_t chunk_bins;        /* temporal bins per spread / x-FFT round */
   int32_t rounds;            /* spread / x-FFT rounds per call */
+  double deconv_range_xy;    /* largest / smallest lateral deconvolution factor over the kept modes */
+  double deconv_range_t;     /* the same for the temporal deapodisation */
 } pat_plan_info;
 
 /* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, window
@@ -141,7 +145,12 @@ pat_status pat_plan_desc_init(pat_plan_desc* desc);
  * and window weights, the spread tile lists, the deconvolution and
  * deapodisation vectors and the FFT twiddles, and copies them to the device
  * with hipMemcpyAsync on `stream` (hipStream_t) followed by a stream
- * synchronisation. On success *out owns the plan; on failure *out is NULL. */
+ * synchronisation. On success *out owns the plan; on failure *out is NULL.
+ * PAT_ERR_UNSUPPORTED also when the lattice's largest |omega| dt is so close
+ * to or beyond pi that no temporal FFT up to 8192 points holds the band, and
+ * for FP32 plans whose deconvolution dynamic range exceeds 1e4 (oversampling
+ * near 1 with wide windows: FP32 rounding would be amplified beyond use; the
+ * FP64 form accepts them). */
 pat_status nufft_plan(const pat_plan_desc* desc, void* stream, pat_plan** out);
 
 /* Workspace bytes every compute call on this plan needs (>= 256-byte aligned). */

@@ -70,6 +70,8 @@ class PlanInfo(C.Structure):
         ("table_bytes", C.c_size_t),
         ("chunk_bins", C.c_int32),
         ("rounds", C.c_int32),
+        ("deconv_range_xy", C.c_double),
+        ("deconv_range_t", C.c_double),
     ]
 
 

@@ -19,6 +19,7 @@ import time
 
 import numpy as np
 
+from ._native import PAT_ERR_UNSUPPORTED, PatError
 from .plan import Plan
 
 SIGMAS = (1.25, 1.5, 2.0)
@@ -75,7 +76,13 @@ class Autotuner:
         tried = []
 
         def err_of(settings):
-            pl = self._plan(problem, self.precision, settings)
+            try:
+                pl = self._plan(problem, self.precision, settings)
+            except PatError as exc:  # refused setting (e.g. FP32 with too wide a deconvolution range)
+                if exc.status != PAT_ERR_UNSUPPORTED:
+                    raise
+                tried.append(dict(settings=settings, rel_err=float("inf")))
+                return float("inf"), None
             out = pl.reconstruct(g)
             torch.cuda.synchronize()
             e = _rel(out, ref)
@@ -101,7 +108,7 @@ class Autotuner:
         for _, a, b in combos:
             settings = dict(sigma_xy=a[2], width_xy=a[1], sigma_t=b[2], width_t=b[1])
             e, _ = err_of(settings)
-            if e > limit:
+            if not e <= limit:
                 continue
             pl = self._plan(problem, self.precision, settings)
             out = torch.empty(pl.shape, dtype=pl.dtype, device=pl.device)

@@ -141,6 +141,29 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.n_y = next_smooth_even(d.sigma_xy * d.ny);
   const bool linear_t = d.temporal_interp == PAT_INTERP_LINEAR;
   dp.n_t = next_smooth_even(d.sigma_t * Nt);
+  // band of oversampled temporal bins the interpolation reads: |K| from 0 (the
+  // l = 0 plane, read by the forward model and the adjoint) to the largest
+  // non-Nyquist lattice point, w_t/2 bins of margin below and w_t/2 + 1
+  // above. Short traces can need more bins than smooth(sigma_t*Nt) holds;
+  // the FFT is then lengthened until the band fits (more oversampling).
+  {
+    const int wt_taps = linear_t ? 2 : d.width_t;
+    const double Kx = (d.nx / 2 - 1) * 2.0 * M_PI / d.lx, Ky = (d.ny / 2 - 1) * 2.0 * M_PI / d.ly;
+    const double Kz = (d.nz / 2 - 1) * 2.0 * M_PI / d.lz;
+    const double kmax = std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+    for (;;) {
+      const double smax = kmax * d.c * d.dt * dp.n_t / (2.0 * M_PI);
+      const long blo = -wt_taps / 2;
+      const long bhi = (long)std::floor(smax) + wt_taps / 2 + 1;
+      if (bhi - blo + 1 <= dp.n_t && bhi < dp.n_t) {
+        dp.b_lo = (int)blo;
+        dp.nb = (int)(bhi - blo + 1);
+        break;
+      }
+      if (dp.n_t >= 8192) return PAT_ERR_UNSUPPORTED;  // |omega| dt near or past pi
+      dp.n_t = next_smooth_even(dp.n_t + 1);
+    }
+  }
   // window form: samples centred on n0 = Nt/2; linear baseline: zeros appended
   // after the trace (time origin 0) and two taps
   dp.n0 = linear_t ? 0 : Nt / 2;
@@ -173,20 +196,6 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.n0_over_nt = double(dp.n0) / double(dp.n_t);
   dp.inv_vol = 1.0 / (d.lx * d.ly * d.lz);
   dp.adj_scale = 0.5 / (double(d.nx) * d.ny * d.nz);
-  // band of oversampled temporal bins read by the interpolation (one bin of
-  // margin each side): |K| from 0 (the l = 0 plane, read by the forward model
-  // and the adjoint) to the largest non-Nyquist lattice point
-  {
-    const double jx = d.nx / 2 - 1, jy = d.ny / 2 - 1, jz = d.nz / 2 - 1;
-    const double Kx = jx * dp.kxu, Ky = jy * dp.kyu, Kz = jz * dp.kzu;
-    const double smax = std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz) * dp.s_per_k;
-    const double smin = 0.0;
-    const long blo = (long)std::floor(smin) - dp.w_t / 2;
-    const long bhi = (long)std::floor(smax) + dp.w_t / 2 + 1;
-    if (bhi - blo + 1 > dp.n_t || blo <= -dp.n_t || bhi >= dp.n_t) return PAT_ERR_UNSUPPORTED;
-    dp.b_lo = (int)blo;
-    dp.nb = (int)(bhi - blo + 1);
-  }
 
   const pathost::Window wxy(d.kernel == PAT_KERNEL_KAISER_BESSEL ? 1 : 0, d.width_xy, d.sigma_xy);
   const pathost::Window wt(d.kernel == PAT_KERNEL_KAISER_BESSEL ? 1 : 0, d.width_t, double(dp.n_t) / Nt);
@@ -301,6 +310,24 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   }
   const size_t o_dcx = add_real<T>(blob, dcx);
   const size_t o_dcy = add_real<T>(blob, dcy);
+  // dynamic range of the deconvolutions (largest over smallest 1/phihat over
+  // the kept modes): FP32 rounding in the grid and the band is amplified by
+  // it, so FP32 plans beyond 1e4 (sigma near 1 with wide windows) are refused
+  {
+    auto range = [](const std::vector<double>& v) {
+      double lo = 0.0, hi = 0.0;
+      for (double a : v) {
+        a = std::fabs(a);
+        if (a == 0.0) continue;
+        lo = lo == 0.0 ? a : std::min(lo, a);
+        hi = std::max(hi, a);
+      }
+      return lo > 0.0 ? hi / lo : 1.0;
+    };
+    P->range_xy = range(dcx) * range(dcy);
+    P->range_t = range(deap);
+    if (sizeof(T) == 4 && (P->range_xy > 1e4 || P->range_t > 1e4)) return PAT_ERR_UNSUPPORTED;
+  }
   // temporal tap polynomials
   std::vector<double> coef;
   const double tol = sizeof(T) == 8 ? 1e-13 : 1e-9;
@@ -577,6 +604,8 @@ pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
   info->table_bytes = P->dev_bytes;
   info->chunk_bins = P->dp.chunk_bins;
   info->rounds = rounds(P->dp);
+  info->deconv_range_xy = P->range_xy;
+  info->deconv_range_t = P->range_t;
   return PAT_OK;
 }
 

@@ -1,0 +1,173 @@
+"""Edge cases of the HIP path through the C ABI, against the FP64 oracle:
+the smallest problem (one sensor, two samples, 4^3 grid), sensors on the
+plane's boundary, the longest temporal FFT (n_t = 8192) and the deepest grid
+(Nz = 2048, the forward model's largest per-column LDS), the narrowest and
+widest windows and the extreme oversampling factors, and all-zero inputs.
+
+Tolerances: FP32 1e-5 relative L2 where the window setting can reach it;
+the FP64 form must match the oracle within a frozen bound over its measured
+window error (2e-1 for w = 2), and the FP32 form must match the FP64 form
+within 1e-5, except where the plan refuses FP32 (sigma 1.1 with w 16, whose
+deconvolution range exceeds 1e4).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import forward_model as fm
+from oracle.quality import rel_l2
+from paper_1510_01078_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+C = 1500.0
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def _run(xy, h, g, nt, dt, shape, extent, precision="fp32", **kw):
+    from paper_1510_01078_amd import Plan
+    pl = Plan(xy, nt, dt, C, shape, extent, sensor_h=h, precision=precision, **kw)
+    gt = torch.from_numpy(np.ascontiguousarray(g)).to(pl.device, pl.dtype)
+    f = pl.reconstruct(gt).cpu().numpy().astype(np.float64)
+    pl.close()
+    return f
+
+
+def test_smallest_problem(dev):
+    """One sensor at the centre, two samples, the minimum 4^3 grid (the plan
+    lengthens the temporal FFT so the interpolation band fits)."""
+    xy = np.zeros((1, 2))
+    h = np.array([4e-6])
+    g = np.array([[1.0, -0.5]])
+    ref = oracle.reconstruct(xy, h, g, 40e-9, C, (4, 4, 4), (2e-3, 2e-3, 2e-3))
+    for precision, tol in (("fp64", 1e-6), ("fp32", 1e-5)):
+        f = _run(xy, h, g, 2, 40e-9, (4, 4, 4), (2e-3, 2e-3, 2e-3), precision)
+        e = rel_l2(f, ref)
+        _say(f"[gpu] 1 sensor, 2 samples, 4^3 {precision}: rel-L2 {e:.3e}")
+        assert e <= tol
+
+
+def test_sensors_on_the_boundary(dev):
+    """Sensors at x = -X/2 and y = -Y/2 exactly (allowed) and just inside +X/2."""
+    X = Y = 4e-3
+    top = np.nextafter(X / 2, 0.0)
+    xy = np.array([[-X / 2, -Y / 2], [-X / 2, 0.0], [0.0, -Y / 2], [top, top], [top, -Y / 2], [0.3e-3, 0.7e-3]])
+    rng = np.random.default_rng(41)
+    g = rng.standard_normal((len(xy), 40))
+    h = np.full(len(xy), X * Y / len(xy))
+    shape, ext = (12, 10, 16), (X, Y, 5e-3)
+    ref = oracle.reconstruct(xy, h, g, 30e-9, C, shape, ext)
+    f = _run(xy, h, g, 40, 30e-9, shape, ext, "fp32")
+    e = rel_l2(f, ref)
+    _say(f"[gpu] boundary sensors fp32: rel-L2 {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_longest_temporal_fft(dev):
+    """Nt = 4096 at sigma_t = 2: n_t = 8192, the temporal kernel's limit."""
+    from paper_1510_01078_amd import Plan
+    rng = np.random.default_rng(42)
+    p = inputs.random_problem(rng, 64, 4096, (16, 16, 16), (4e-3, 4e-3, 4e-3), dt=10e-9)
+    ref = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32", sigma_t=2.0)
+    assert pl.info["nt_over"] == 8192
+    f = pl.reconstruct(torch.from_numpy(p.g).to(pl.device, torch.float32)).cpu().numpy().astype(np.float64)
+    pl.close()
+    e = rel_l2(f, ref)
+    _say(f"[gpu] Nt 4096 (n_t 8192) fp32: rel-L2 {e:.3e}")
+    assert e <= 1e-5
+
+
+def test_deepest_grid_reconstruct_and_forward(dev):
+    """Nz = 2048 (Lz = 1024 depth modes per lateral column in the forward
+    model's transposed interpolation, the largest LDS it uses)."""
+    from paper_1510_01078_amd import Plan
+    rng = np.random.default_rng(43)
+    shape, ext = (4, 6, 2048), (2e-3, 3e-3, 40e-3)
+    m, nt, dt = 16, 64, 10e-9  # c dt below the depth step: the deepest |omega| dt stays below pi
+    xy = np.stack([rng.uniform(-1e-3, 1e-3, m), rng.uniform(-1.5e-3, 1.5e-3, m)], 1)
+    h = np.full(m, 6e-6 / m)
+    g = rng.standard_normal((m, nt))
+    f_img = rng.standard_normal(shape)
+    ref = oracle.reconstruct(xy, h, g, dt, C, shape, ext)
+    ref_a = fm.forward(f_img, xy, nt, dt, C, ext)
+    ref_s = fm.adjoint(g, xy, dt, C, shape, ext)
+    pl = Plan(xy, nt, dt, C, shape, ext, sensor_h=h, precision="fp64")
+    gt = torch.from_numpy(g).to(pl.device, torch.float64)
+    ft = torch.from_numpy(f_img).to(pl.device, torch.float64)
+    e = [rel_l2(pl.reconstruct(gt).cpu().numpy(), ref), rel_l2(pl.forward(ft).cpu().numpy(), ref_a),
+         rel_l2(pl.adjoint(gt).cpu().numpy(), ref_s)]
+    pl.close()
+    _say(f"[gpu] Nz 2048 fp64: R {e[0]:.3e} A {e[1]:.3e} A* {e[2]:.3e}")
+    assert max(e) <= 1e-6
+
+
+# (settings, FP64 bound over the measured window error, FP32 accepted):
+# measured FP64 errors 7.6e-2 (w 2), 4.8e-15 (w 16, sigma 4), 4.9e-9 (w 16,
+# sigma 1.1), 7.2e-9 (Gaussian w 16). At sigma 1.1 with w 16 the
+# deconvolution spans ~1e5 per axis and FP32 came out 0.6 off the FP64 form,
+# so FP32 plans there are refused.
+@pytest.mark.parametrize("kw,bound64,fp32_ok", [
+    (dict(kernel="kaiser_bessel", width_xy=2, width_t=2, sigma_xy=2.0, sigma_t=2.0), 0.2, True),
+    (dict(kernel="kaiser_bessel", width_xy=16, width_t=16, sigma_xy=4.0, sigma_t=4.0), 1e-12, True),
+    (dict(kernel="kaiser_bessel", width_xy=16, width_t=16, sigma_xy=1.1, sigma_t=1.1), 1e-8, False),
+    (dict(kernel="gaussian", width_xy=16, width_t=16, sigma_xy=2.0, sigma_t=2.0), 1e-7, True),
+], ids=["w2", "w16_sigma4", "w16_sigma1.1", "gauss16"])
+def test_window_extremes(dev, kw, bound64, fp32_ok):
+    from paper_1510_01078_amd import Plan
+    from paper_1510_01078_amd._native import PatError, PAT_ERR_UNSUPPORTED
+    rng = np.random.default_rng(44)
+    p = inputs.random_problem(rng, 150, 61, (12, 16, 10), (3e-3, 4e-3, 3e-3), dt=30e-9)
+    ref = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+    f64 = _run(p.xy, p.h, p.g, p.nt, p.dt, p.shape, p.extent, "fp64", **kw)
+    e64 = rel_l2(f64, ref)
+    if fp32_ok:
+        f32 = _run(p.xy, p.h, p.g, p.nt, p.dt, p.shape, p.extent, "fp32", **kw)
+        e32_64 = rel_l2(f32, f64)
+    else:
+        with pytest.raises(PatError) as err:
+            Plan(p.xy, p.nt, p.dt, C, p.shape, p.extent, sensor_h=p.h, precision="fp32", **kw)
+        assert err.value.status == PAT_ERR_UNSUPPORTED
+        e32_64 = float("nan")
+    _say(f"[gpu] window {kw}: fp64 vs oracle {e64:.3e}, fp32 vs fp64 {e32_64:.3e}")
+    assert e64 <= bound64
+    assert not fp32_ok or e32_64 <= 1e-5
+
+
+def test_deconvolution_range_reported(dev):
+    """The benchmark setting's deconvolution ranges, reported by the plan."""
+    from paper_1510_01078_amd import Plan
+    p = inputs.config_problem(1)
+    pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32", kernel="kaiser_bessel",
+              sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+    rx, rt = pl.info["deconv_range_xy"], pl.info["deconv_range_t"]
+    pl.close()
+    _say(f"[gpu] benchmark setting deconvolution ranges: lateral {rx:.1f}, temporal {rt:.1f}")
+    assert 1.0 < rx < 1e4 and 1.0 < rt < 1e4
+
+
+def test_zero_inputs_give_exact_zeros(dev):
+    from paper_1510_01078_amd import Plan
+    rng = np.random.default_rng(45)
+    p = inputs.random_problem(rng, 50, 32, (8, 8, 8), (2e-3, 2e-3, 2e-3), dt=30e-9)
+    pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32")
+    z = torch.zeros((p.m, p.nt), device=pl.device)
+    zi = torch.zeros(p.shape, device=pl.device)
+    outs = [pl.reconstruct(z), pl.adjoint(z), pl.forward(zi), pl.spectrum(z)]
+    torch.cuda.synchronize()
+    pl.close()
+    assert all(bool((o == 0).all()) for o in outs)
