@@ -133,6 +133,10 @@ typedef struct pat_plan_info {
   int32_t rounds;            /* spread / x-FFT rounds per call */
   double deconv_range_xy;    /* largest / smallest lateral deconvolution factor over the kept modes */
   double deconv_range_t;     /* the same for the temporal deapodisation */
+  int32_t forward_fused;     /* 1: the forward model's x-FFT and interpolation to the sensors run as one
+                                kernel with no grid buffer (oversampled x length <= 1024 and a strip of
+                                16 + width_xy - 1 grid rows fits the work-group LDS); 0: two kernels in
+                                rounds of chunk_bins bins */
 } pat_plan_info;
 
 /* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, window
@@ -271,7 +275,8 @@ pat_status pat_batch_destroy(pat_batch* batch);
  * of pat_forward and pat_forward_dxy add each kernel's time to the stage it
  * transposes (5: forward 3-D FFT, 4: transposed interpolation, 3 and 2:
  * transposed lateral FFTs, 1: interpolation to the sensors, 0: transposed
- * temporal FFT). */
+ * temporal FFT); with pat_plan_info.forward_fused the fused x-FFT and
+ * interpolation kernel counts under stage 1 and stage 2 reads 0. */
 #define PAT_TIMING_STAGES 6
 pat_status pat_timing_begin(pat_plan* plan, int32_t max_calls);
 pat_status pat_timing_end(pat_plan* plan, double* ms, int32_t nstage, int32_t* calls);

@@ -72,6 +72,7 @@ class PlanInfo(C.Structure):
         ("rounds", C.c_int32),
         ("deconv_range_xy", C.c_double),
         ("deconv_range_t", C.c_double),
+        ("forward_fused", C.c_int32),
     ]
 
 

@@ -407,6 +407,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t sz_Gh = size_t(d.nx) * d.ny * dp.nb * c;
   const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
   P->forward_ok = patk::scatter_lds_bytes<T>(dp) <= (size_t)lds_limit;
+  P->forward_fused = patk::fused_interp_ok<T>(dp, (size_t)lds_limit);
   const size_t szA = align_up(std::max(sz_U, sz_Gh));
   const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;
@@ -491,12 +492,17 @@ pat_status run_image_in(pat_plan* P, const void* f, void* g, void* ws, hipStream
   mark(4);
   if ((e = patk::launch_fft_y_t<T>(dp, A, B, s)) != hipSuccess) return to_status(e);
   mark(3);
-  for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
-    const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
-    if ((e = patk::launch_fft_x_t<T>(dp, B, A, b0, b1, s)) != hipSuccess) return to_status(e);
-    mark(2);
-    if ((e = patk::launch_interp<T>(dp, A, C, b0, b1, s)) != hipSuccess) return to_status(e);
+  if (P->forward_fused) {
+    if ((e = patk::launch_fft_x_interp<T>(dp, B, C, s)) != hipSuccess) return to_status(e);
     mark(1);
+  } else {
+    for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
+      const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
+      if ((e = patk::launch_fft_x_t<T>(dp, B, A, b0, b1, s)) != hipSuccess) return to_status(e);
+      mark(2);
+      if ((e = patk::launch_interp<T>(dp, A, C, b0, b1, s)) != hipSuccess) return to_status(e);
+      mark(1);
+    }
   }
   if ((e = patk::launch_temporal_t<T>(dp, C, static_cast<T*>(g), s)) != hipSuccess) return to_status(e);
   mark(0);
@@ -606,6 +612,7 @@ pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
   info->rounds = rounds(P->dp);
   info->deconv_range_xy = P->range_xy;
   info->deconv_range_t = P->range_t;
+  info->forward_fused = P->forward_fused ? 1 : 0;
   return PAT_OK;
 }
 

@@ -3,6 +3,7 @@
 // eq. NED_NUFFT), used by the forward model.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels_common.hpp"
@@ -119,7 +120,189 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
   return hipGetLastError();
 }
 
-#define PATK_INST(T) template hipError_t launch_interp<T>(const DevPlan&, const void*, void*, int, int, hipStream_t);
+// ---------------------------------------------------------------------------
+// Fused form of k_fft_x_t followed by k_interp: the oversampled grid U' never
+// goes to memory. A work-group owns one strip of kSpreadTile grid rows (a row
+// of home tiles) and a run of bins. Per bin it loads the strip's rows plus a
+// (W-1)-row halo of V' (periodic in y), embeds the Nx kept modes of every row
+// into n_x slots, inverse-FFTs the rows in LDS (one wave per row), then
+// interpolates every sensor whose footprint origin lies in the strip straight
+// from LDS. Per sensor the footprint sum runs in the same order as k_interp,
+// and the row transforms are those of k_fft_x_t, so both forms give the same
+// bits.
+// ---------------------------------------------------------------------------
+constexpr int kFusedThreads = 512;
+
+template <int W>
+__host__ __device__ constexpr int fused_rows() { return kSpreadTile + W - 1; }
+
+// Sensors a thread keeps in registers across the bins of its work-group
+// (footprint origin, columns and weights); sensors of a strip beyond
+// kFusedKeep * kFusedThreads are reloaded per bin.
+// One sensor of the strip: footprint origin row within the strip, the LDS
+// slots of its footprint columns, and its weights.
+template <typename T, int W>
+struct FusedSensor {
+  int m, oy;
+  int col[W];
+  T wx[W], wy[W];
+};
+
+template <typename T, int W>
+__device__ __forceinline__ void fused_sensor_load(FusedSensor<T, W>& f, int m, int py0, int n_x,
+                                                  const int* __restrict__ sbx, const int* __restrict__ sby,
+                                                  const T* __restrict__ swx, const T* __restrict__ swy) {
+  f.m = m;
+  const int ox = sbx[m];
+  f.oy = sby[m] - py0;
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    f.wx[t] = swx[size_t(m) * W + t];
+    f.wy[t] = swy[size_t(m) * W + t];
+    int c = ox + t;
+    if (c >= n_x) c -= n_x;
+    f.col[t] = lpos(c);
+  }
+}
+
+// footprint sum in k_interp's order: rows of x-weighted sums, then y weights
+template <typename T, int W>
+__device__ __forceinline__ cx<T> fused_sensor_sum(const FusedSensor<T, W>& f, const cx<T>* buf, int bstride) {
+  const cx<T>* rows = buf + f.oy * bstride;
+  cx<T> acc{T(0), T(0)};
+#pragma unroll
+  for (int ty = 0; ty < W; ++ty) {
+    cx<T> row{T(0), T(0)};
+#pragma unroll
+    for (int tx = 0; tx < W; ++tx) {
+      const cx<T> v = rows[ty * bstride + f.col[tx]];
+      row.x += f.wx[tx] * v.x;
+      row.y += f.wx[tx] * v.y;
+    }
+    acc.x += f.wy[ty] * row.x;
+    acc.y += f.wy[ty] * row.y;
+  }
+  return acc;
+}
+
+template <typename T, int W, int MAXV>
+__global__ __launch_bounds__(kFusedThreads) void k_fft_x_interp(
+    const cx<T>* __restrict__ V, int nb, int Nx, int n_y, int tiles_x, int nchunks, int bins,
+    const int* __restrict__ home_off, const int* __restrict__ home_sens, const int* __restrict__ sbx,
+    const int* __restrict__ sby, const T* __restrict__ swx, const T* __restrict__ swy, FftDesc<T> fd,
+    cx<T>* __restrict__ Gt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  constexpr int R = fused_rows<W>();
+  const int chunk = blockIdx.x % nchunks;  // bins vary fastest: neighbouring groups share the strip's sensors
+  const int strip = blockIdx.x / nchunks;
+  const int q0 = home_off[strip * tiles_x], q1 = home_off[(strip + 1) * tiles_x];
+  if (q0 == q1) return;
+  const int n_x = fd.n;
+  const int bstride = lseq(n_x);
+  const int py0 = strip * kSpreadTile;
+  const int b0 = chunk * bins, b1 = min(nb, b0 + bins);
+  const int gap = n_x - Nx;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+  const FastDiv div_gap(gap > 0 ? gap : 1), div_r(R);
+  const size_t plane = size_t(Nx) * n_y;
+  const int total = R * Nx;
+  for (int b = b0; b < b1; ++b) {
+    for (int q = tid; q < R * gap; q += nthr) {
+      const int r = div_gap(q);
+      buf[r * bstride + lpos(Nx / 2 + (q - r * gap))] = cx<T>{T(0), T(0)};
+    }
+    // element q of the strip: mode jj = q / R of grid row py0 + q mod R (periodic in y)
+    const cx<T>* src = V + size_t(b) * plane;
+    constexpr int kStage = 8;
+    for (int qs = 0; qs < total; qs += kStage * nthr) {
+      cx<T> v[kStage];
+      int dst[kStage];
+#pragma unroll
+      for (int u = 0; u < kStage; ++u) {
+        const int q = qs + tid + u * nthr;
+        dst[u] = -1;
+        if (q < total) {
+          const int jj = div_r(q);
+          const int r = q - jj * R;
+          int py = py0 + r;
+          while (py >= n_y) py -= n_y;
+          v[u] = src[size_t(jj) * n_y + py];
+          const int j = jj < Nx / 2 ? jj : jj - Nx;
+          dst[u] = r * bstride + lpos(j < 0 ? j + n_x : j);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        if (dst[u] >= 0) buf[dst[u]] = v[u];
+    }
+    __syncthreads();
+    for (int r = wave; r < R; r += nwaves) fft_lds<T, MAXV, true, true>(buf + r * bstride, fd, 1, bstride, lane, 64);
+    __syncthreads();
+    for (int q = q0 + tid; q < q1; q += nthr) {
+      FusedSensor<T, W> f;
+      fused_sensor_load<T, W>(f, home_sens[q], py0, n_x, sbx, sby, swx, swy);
+      Gt[size_t(f.m) * nb + b] = fused_sensor_sum<T, W>(f, buf, bstride);
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+size_t fused_interp_lds(const DevPlan& p) {
+  return size_t(kSpreadTile + p.w_xy - 1) * lseq(p.n_x) * sizeof(cx<T>);
+}
+
+template <typename T>
+bool fused_interp_ok(const DevPlan& p, size_t lds_limit) {
+  return p.n_x <= kWaveFftMax && p.w_xy >= 2 && p.w_xy <= 16 && (p.w_xy % 2) == 0 && p.Nx <= p.n_x &&
+         fused_interp_lds<T>(p) <= lds_limit;
+}
+
+template <typename T, int W, int MAXV>
+static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
+  const size_t lds = fused_interp_lds<T>(p);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_interp<T, W, MAXV>), lds);
+  if (e != hipSuccess) return e;
+  // bins per work-group: enough groups to fill the device several times over
+  const long long strips = p.tiles_y;
+  int bins = int(std::min<long long>(8, std::max<long long>(1, strips * p.nb / 2048)));
+  const int nchunks = (p.nb + bins - 1) / bins;
+  const long long blocks = strips * nchunks;
+  hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV>), dim3((unsigned)blocks), dim3(kFusedThreads), lds, s,
+                     static_cast<const cx<T>*>(V), p.nb, p.Nx, p.n_y, p.tiles_x, nchunks, bins, p.home_off,
+                     p.home_sens, p.sbx, p.sby, static_cast<const T*>(p.swx), static_cast<const T*>(p.swy),
+                     as_desc<T>(p.f_nx), static_cast<cx<T>*>(Gt));
+  return hipGetLastError();
+}
+
+// rows of up to 512 points need 8 values per lane in the one-wave transform, longer ones 16
+template <typename T, int W>
+static hipError_t launch_fused_w(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
+  return p.n_x <= 512 ? launch_fused_wv<T, W, 8>(p, V, Gt, s) : launch_fused_wv<T, W, 16>(p, V, Gt, s);
+}
+
+template <typename T>
+hipError_t launch_fft_x_interp(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
+  if (p.n_x > kWaveFftMax || p.Nx > p.n_x) return hipErrorInvalidValue;
+  switch (p.w_xy) {
+    case 2: return launch_fused_w<T, 2>(p, V, Gt, s);
+    case 4: return launch_fused_w<T, 4>(p, V, Gt, s);
+    case 6: return launch_fused_w<T, 6>(p, V, Gt, s);
+    case 8: return launch_fused_w<T, 8>(p, V, Gt, s);
+    case 10: return launch_fused_w<T, 10>(p, V, Gt, s);
+    case 12: return launch_fused_w<T, 12>(p, V, Gt, s);
+    case 14: return launch_fused_w<T, 14>(p, V, Gt, s);
+    case 16: return launch_fused_w<T, 16>(p, V, Gt, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define PATK_INST(T) template hipError_t launch_interp<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
+  template hipError_t launch_fft_x_interp<T>(const DevPlan&, const void*, void*, hipStream_t);                   \
+  template size_t fused_interp_lds<T>(const DevPlan&);                                                        \
+  template bool fused_interp_ok<T>(const DevPlan&, size_t);
 PATK_INST(float)
 PATK_INST(double)
 #undef PATK_INST

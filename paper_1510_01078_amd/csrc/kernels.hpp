@@ -112,6 +112,15 @@ hipError_t launch_fft_x_t(const DevPlan& p, const void* V, void* U, int b_begin,
 // U' (bins [b_begin, b_end)) -> Gt'[m][b] at the sensors
 template <typename T>
 hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin, int b_end, hipStream_t s);
+// k_fft_x_t and k_interp in one kernel over all bins (no grid buffer); usable
+// when fused_interp_ok: n_x <= 1024 and the strip of 16 + w - 1 rows fits the
+// work-group LDS limit.
+template <typename T>
+hipError_t launch_fft_x_interp(const DevPlan& p, const void* V, void* Gt, hipStream_t s);
+template <typename T>
+size_t fused_interp_lds(const DevPlan& p);
+template <typename T>
+bool fused_interp_ok(const DevPlan& p, size_t lds_limit);
 // Gt' -> g[m][n] (unit weights)
 template <typename T>
 hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s);

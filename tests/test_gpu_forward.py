@@ -112,6 +112,27 @@ def test_gpu_pair_adjointness(dev, precision, tol):
     assert abs(lhs - rhs) <= tol * scale
 
 
+@pytest.mark.parametrize("precision,width,fused,tol", [
+    ("fp64", 16, 0, 1e-10), ("fp64", 8, 1, 1e-6), ("fp32", 16, 1, 1e-5)],
+    ids=["fp64-w16-two-kernel", "fp64-w8-fused", "fp32-w16-fused"])
+def test_forward_fused_and_two_kernel_paths(dev, precision, width, fused, tol):
+    """Oversampled x length 320: the strip of 16 + w - 1 rows that the fused
+    x-FFT + interpolation kernel holds in LDS fits for FP32 and for FP64 with
+    w = 8, not for FP64 with w = 16, which takes the two-kernel form. Both
+    forms against the oracle."""
+    p = _problem(seed=33, m=40, nt=24, shape=(160, 12, 8), extent=(8e-3, 3e-3, 2e-3))
+    ref = fm.forward(p["f"], p["xy"], p["nt"], p["dt"], C, p["extent"])
+    pl = _plan(p, precision, kernel="kaiser_bessel", sigma_xy=2.0, width_xy=width, sigma_t=2.0, width_t=width)
+    assert pl.info["nx_over"] == 320
+    path = pl.info["forward_fused"]
+    A = pl.forward(_t(p["f"], pl)).cpu().numpy().astype(np.float64)
+    pl.close()
+    e = rel_l2(A, ref)
+    _say(f"[gpu] forward n_x 320 {precision} w{width}: fused={path} rel-L2 {e:.3e}")
+    assert path == fused
+    assert e <= tol
+
+
 def test_plane_wave_headline_geometry(dev):
     """At the benchmark's size (128x128 warped sensors, 2048 samples, 256^3),
     a lattice plane wave must come back as the standing wave
@@ -122,6 +143,7 @@ def test_plane_wave_headline_geometry(dev):
     X, Y, Z = p.extent
     pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32", kernel="kaiser_bessel",
               sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+    assert pl.info["forward_fused"] == 1
     x = (np.arange(Nx) - Nx / 2) * X / Nx
     y = (np.arange(Ny) - Ny / 2) * Y / Ny
     z = np.arange(Nz) * Z / Nz
