@@ -91,6 +91,7 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
   const int P = int(G.members.size());
   const size_t c = sizeof(cx<T>);
   const patk::FftCfg cfg = patk::fft_cfg();
+  const patk::FftCfg icfg = patk::inv_cfg();
   std::vector<patk::TemporalBA> a0(P);
   std::vector<patk::SpreadBA> a1(P);
   std::vector<patk::FftXBA> a2(P);
@@ -141,18 +142,18 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
                            d.s_per_k, d.kxu, d.kyu, d.kzu, d.two_c, d.n0_over_nt, d.inv_vol, Bw};
     pre[4][p + 1] = int((size_t(d.Nx) * d.Ny * Lh + 255) / 256);
     // stages 5, 6: inverse transforms along x and y (in place on the spectrum)
-    const int lcx = patk::fft_batch<T>(d.Nx, cfg.threads, cfg.cap);
+    const int lcx = patk::fft_batch<T>(d.Nx, icfg.threads, icfg.cap);
     const int gx5 = (Lh + lcx - 1) / lcx;
     a5[p] = patk::CfftBA{Bw, patk::as_view(d.f_Nx), d.Ny, Lh, lcx, gx5};
     pre[5][p + 1] = gx5 * d.Ny;
     lds[5] = std::max(lds[5], size_t(lcx) * patk::lseq(d.Nx) * c);
-    const int lcy = patk::fft_batch<T>(d.Ny, cfg.threads, cfg.cap);
+    const int lcy = patk::fft_batch<T>(d.Ny, icfg.threads, icfg.cap);
     const int gx6 = (Lh + lcy - 1) / lcy;
     a6[p] = patk::CfftBA{Bw, patk::as_view(d.f_Ny), d.Ny, Lh, lcy, gx6};
     pre[6][p + 1] = gx6 * d.Nx;
     lds[6] = std::max(lds[6], size_t(lcy) * patk::lseq(d.Ny) * c);
     // stage 7: complex-to-real along z into the caller's image
-    const int rz = patk::fft_batch<T>(d.Nz, cfg.threads, cfg.cap);
+    const int rz = patk::fft_batch<T>(d.Nz, icfg.threads, icfg.cap);
     const long long nrows = (long long)d.Nx * d.Ny;
     a7[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
     pre[7][p + 1] = int((nrows + rz - 1) / rz);

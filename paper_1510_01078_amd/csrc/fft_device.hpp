@@ -257,4 +257,130 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int bat
   }
 }
 
+// ---------------------------------------------------------------------------
+// Compile-time form for one length N: the same passes (radices taken greedily
+// in the order 8, 4, 2, 5, 3, as the host planner does), twiddle reads and
+// butterflies as fft_lds with the host plan for N, so the results are the
+// same; with N, the radix, p and the butterfly count known to the compiler,
+// the index arithmetic folds to constants and the LDS offsets of a
+// butterfly's R inputs and outputs become instruction immediates where the
+// pad pattern allows (strides that are multiples of 8 slots). Sequences sit
+// lseq(N) slots apart. NT threads cooperate on at most MAXB sequences
+// (WAVE = true: one wave, nthr = 64, wave-local ordering only).
+// ---------------------------------------------------------------------------
+struct CtPlan {
+  int np;
+  int r[16];
+};
+
+__host__ __device__ constexpr CtPlan ct_plan(int n) {
+  CtPlan c{0, {}};
+  const int rs[5] = {8, 4, 2, 5, 3};
+  int m = n;
+  for (int q = 0; q < 5; ++q)
+    while (m % rs[q] == 0 && c.np < 16) {
+      c.r[c.np++] = rs[q];
+      m /= rs[q];
+    }
+  return c;
+}
+
+__host__ __device__ constexpr int ct_prefix(int n, int s) {
+  const CtPlan c = ct_plan(n);
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= c.r[i];
+  return p;
+}
+
+template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE>
+__device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+  constexpr CtPlan pl = ct_plan(N);
+  constexpr int R = pl.r[S];
+  constexpr int P = ct_prefix(N, S);
+  constexpr int NBF = N / R;
+  constexpr int TWS = N / (P * R);
+  constexpr int BS = lseq(N);
+  constexpr int K = (NBF * MAXB + NT - 1) / NT;
+  const int total = NBF * batch;
+  cx<T> v[K][R];
+#pragma unroll
+  for (int it = 0; it < K; ++it) {
+    const int idx = tid + it * NT;
+    if (idx < total) {
+      const int f = idx / NBF;
+      const int i = idx - f * NBF;
+      const cx<T>* src = buf + f * BS;
+      if constexpr (NBF % 8 == 0) {
+        const cx<T>* s0 = src + lpos(i);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = s0[r * (NBF + NBF / 8)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = src[lpos(i + r * NBF)];
+      }
+      if constexpr (P > 1) {
+        const int k = i % P;
+        if (k != 0) {
+          const int ts = k * TWS;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cx<T> w = tw[r * ts];
+            if (INV) w.y = -w.y;
+            v[it][r] = cmul(v[it][r], w);
+          }
+        }
+      }
+      Dft<T, R, INV>::run(v[it]);
+    }
+  }
+  fft_sync<WAVE>();
+#pragma unroll
+  for (int it = 0; it < K; ++it) {
+    const int idx = tid + it * NT;
+    if (idx < total) {
+      const int f = idx / NBF;
+      const int i = idx - f * NBF;
+      cx<T>* dst = buf + f * BS;
+      if constexpr (P == 1) {
+        // j0 = i*R; for R = 8 the outputs r land at 9i + r, else lpos per output
+        if constexpr (R == 8) {
+          cx<T>* d0 = dst + 9 * i;
+#pragma unroll
+          for (int r = 0; r < R; ++r) d0[r] = v[it][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) dst[lpos(i * R + r)] = v[it][r];
+        }
+      } else {
+        const int k = i % P;
+        const int j0 = (i - k) * R + k;
+        if constexpr (P % 8 == 0) {
+          cx<T>* d0 = dst + lpos(j0);
+#pragma unroll
+          for (int r = 0; r < R; ++r) d0[r * (P + P / 8)] = v[it][r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) dst[lpos(j0 + r * P)] = v[it][r];
+        }
+      }
+    }
+  }
+  fft_sync<WAVE>();
+}
+
+template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE>
+__device__ __forceinline__ void ct_passes(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+  if constexpr (S < ct_plan(N).np) {
+    ct_pass<T, N, S, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
+    ct_passes<T, N, S + 1, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
+  }
+}
+
+// Transform `batch` (<= MAXB) sequences of length N at buf + f*lseq(N).
+template <typename T, int N, int NT, int MAXB, bool INV, bool WAVE = false>
+__device__ __forceinline__ void fft_ct(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+  static_assert(ct_prefix(N, ct_plan(N).np) == N, "length must factor into 2, 3, 5");
+  ct_passes<T, N, 0, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
+}
+
 }  // namespace patk

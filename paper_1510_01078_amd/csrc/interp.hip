@@ -185,7 +185,7 @@ __device__ __forceinline__ cx<T> fused_sensor_sum(const FusedSensor<T, W>& f, co
   return acc;
 }
 
-template <typename T, int W, int MAXV>
+template <typename T, int W, int MAXV, int NCT>
 __global__ __launch_bounds__(kFusedThreads) void k_fft_x_interp(
     const cx<T>* __restrict__ V, int nb, int Nx, int n_y, int tiles_x, int nchunks, int bins,
     const int* __restrict__ home_off, const int* __restrict__ home_sens, const int* __restrict__ sbx,
@@ -238,7 +238,12 @@ __global__ __launch_bounds__(kFusedThreads) void k_fft_x_interp(
         if (dst[u] >= 0) buf[dst[u]] = v[u];
     }
     __syncthreads();
-    for (int r = wave; r < R; r += nwaves) fft_lds<T, MAXV, true, true>(buf + r * bstride, fd, 1, bstride, lane, 64);
+    for (int r = wave; r < R; r += nwaves) {
+      if constexpr (NCT > 0)
+        fft_ct<T, NCT, 64, 1, true, true>(buf + r * bstride, 1, fd.tw, lane);
+      else
+        fft_lds<T, MAXV, true, true>(buf + r * bstride, fd, 1, bstride, lane, 64);
+    }
     __syncthreads();
     for (int q = q0 + tid; q < q1; q += nthr) {
       FusedSensor<T, W> f;
@@ -260,17 +265,17 @@ bool fused_interp_ok(const DevPlan& p, size_t lds_limit) {
          fused_interp_lds<T>(p) <= lds_limit;
 }
 
-template <typename T, int W, int MAXV>
+template <typename T, int W, int MAXV, int NCT>
 static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
   const size_t lds = fused_interp_lds<T>(p);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_interp<T, W, MAXV>), lds);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_interp<T, W, MAXV, NCT>), lds);
   if (e != hipSuccess) return e;
   // bins per work-group: enough groups to fill the device several times over
   const long long strips = p.tiles_y;
   int bins = int(std::min<long long>(8, std::max<long long>(1, strips * p.nb / 2048)));
   const int nchunks = (p.nb + bins - 1) / bins;
   const long long blocks = strips * nchunks;
-  hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV>), dim3((unsigned)blocks), dim3(kFusedThreads), lds, s,
+  hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV, NCT>), dim3((unsigned)blocks), dim3(kFusedThreads), lds, s,
                      static_cast<const cx<T>*>(V), p.nb, p.Nx, p.n_y, p.tiles_x, nchunks, bins, p.home_off,
                      p.home_sens, p.sbx, p.sby, static_cast<const T*>(p.swx), static_cast<const T*>(p.swy),
                      as_desc<T>(p.f_nx), static_cast<cx<T>*>(Gt));
@@ -280,7 +285,13 @@ static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hip
 // rows of up to 512 points need 8 values per lane in the one-wave transform, longer ones 16
 template <typename T, int W>
 static hipError_t launch_fused_w(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
-  return p.n_x <= 512 ? launch_fused_wv<T, W, 8>(p, V, Gt, s) : launch_fused_wv<T, W, 16>(p, V, Gt, s);
+  return ct_pick(CtLateral{}, p.n_x, [&](auto c) {
+    constexpr int NCT = decltype(c)::value;
+    if constexpr (NCT > 0)
+      return launch_fused_wv<T, W, 8, NCT>(p, V, Gt, s);
+    else
+      return p.n_x <= 512 ? launch_fused_wv<T, W, 8, 0>(p, V, Gt, s) : launch_fused_wv<T, W, 16, 0>(p, V, Gt, s);
+  });
 }
 
 template <typename T>

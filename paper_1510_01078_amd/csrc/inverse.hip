@@ -13,7 +13,7 @@ namespace patk {
 // half spectrum Fh[jj][kk][l], l = 0..Nz/2: in-place inverse transforms
 // along x and along y, then a complex-to-real transform along z.
 // ---------------------------------------------------------------------------
-template <typename T, bool INV>
+template <typename T, bool INV, int NCT = 0>
 __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
                                             FftDesc<T> fd, int wm, int bx, int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -36,7 +36,10 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
   __syncthreads();
-  fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, fd.tw, tid);
+  else
+    fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
@@ -50,13 +53,13 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
       });
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
                                                       FftDesc<T> fd, int wm) {
-  cfft_x_body<T, INV>(F, Ny, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+  cfft_x_body<T, INV, NCT>(F, Ny, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, int NCT = 0>
 __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm, int bx,
                                             int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -80,7 +83,10 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
   __syncthreads();
-  fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, fd.tw, tid);
+  else
+    fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
@@ -94,13 +100,13 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
       });
 }
 
-template <typename T, bool INV>
+template <typename T, bool INV, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd,
                                                       int wm) {
-  cfft_y_body<T, INV>(F, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+  cfft_y_body<T, INV, NCT>(F, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
 }
 
-template <typename T>
+template <typename T, int NCT = 0>
 __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long long nrows, int rows,
                                            FftDesc<T> fd, T* __restrict__ f, int wm, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -121,7 +127,10 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
         if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
       });
   __syncthreads();
-  fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nr, fd.tw, tid);
+  else
+    fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr,
@@ -132,15 +141,15 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
       [&](int q, T v) { f[r0 * Nz + q] = v; });
 }
 
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__ F, long long nrows, int rows,
                                                      FftDesc<T> fd, T* __restrict__ f, int wm) {
-  c2r_z_body<T>(F, nrows, rows, fd, f, wm, blockIdx.x);
+  c2r_z_body<T, NCT>(F, nrows, rows, fd, f, wm, blockIdx.x);
 }
 
 // Transpose of k_c2r_z for the forward model: real rows f[r][e] ->
 // Dh[r][l] = sum_e f[r][e] exp(-2 pi i l e/Nz), l = 0..Nz/2.
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, long long nrows, int rows,
                                                      FftDesc<T> fd, cx<T>* __restrict__ D) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -159,7 +168,10 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
         buf[r * bstride + lpos(q - r * Nz)] = cx<T>{v, T(0)};
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, false, false>(buf, fd, nr, bstride, tid, nthr);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), false>(buf, nr, fd.tw, tid);
+  else
+    fft_lds<T, kFftMaxV, false, false>(buf, fd, nr, bstride, tid, nthr);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Lh, tid, nthr,
@@ -174,26 +186,36 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
 template <typename T, bool INV>
 static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_t s) {
   const int Lh = p.Nz / 2 + 1;
-  const FftCfg cfg = fft_cfg();
+  const FftCfg cfg = inv_cfg();
   for (int pass = 0; pass < 2; ++pass) {
     const bool along_x = (pass == 0) == x_first;
     hipError_t e;
     if (along_x) {
       const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
       const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_cfft_x<T, INV>), lds)) != hipSuccess) return e;
-      dim3 grid((Lh + lc - 1) / lc, p.Ny);
-      hipLaunchKernelGGL((k_cfft_x<T, INV>), grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc, as_desc<T>(p.f_Nx),
-                         cfg.wave);
+      e = ct_pick(CtInverse{}, p.Nx, [&](auto c) {
+        const void* kern = reinterpret_cast<const void*>(&k_cfft_x<T, INV, decltype(c)::value>);
+        hipError_t e2 = allow_lds(kern, lds);
+        if (e2 != hipSuccess) return e2;
+        dim3 grid((Lh + lc - 1) / lc, p.Ny);
+        hipLaunchKernelGGL((k_cfft_x<T, INV, decltype(c)::value>), grid, dim3(cfg.threads), lds, s, F, p.Ny, Lh, lc,
+                           as_desc<T>(p.f_Nx), cfg.wave);
+        return hipGetLastError();
+      });
     } else {
       const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
       const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
-      if ((e = allow_lds(reinterpret_cast<const void*>(&k_cfft_y<T, INV>), lds)) != hipSuccess) return e;
-      dim3 grid((Lh + lc - 1) / lc, p.Nx);
-      hipLaunchKernelGGL((k_cfft_y<T, INV>), grid, dim3(cfg.threads), lds, s, F, Lh, lc, as_desc<T>(p.f_Ny),
-                         cfg.wave);
+      e = ct_pick(CtInverse{}, p.Ny, [&](auto c) {
+        const void* kern = reinterpret_cast<const void*>(&k_cfft_y<T, INV, decltype(c)::value>);
+        hipError_t e2 = allow_lds(kern, lds);
+        if (e2 != hipSuccess) return e2;
+        dim3 grid((Lh + lc - 1) / lc, p.Nx);
+        hipLaunchKernelGGL((k_cfft_y<T, INV, decltype(c)::value>), grid, dim3(cfg.threads), lds, s, F, Lh, lc,
+                           as_desc<T>(p.f_Ny), cfg.wave);
+        return hipGetLastError();
+      });
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -203,30 +225,37 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   cx<T>* F = static_cast<cx<T>*>(Fh);
   hipError_t e = launch_xy<T, true>(p, F, true, s);
   if (e != hipSuccess) return e;
-  const FftCfg cfg = fft_cfg();
+  const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
   const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
-  if ((e = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T>), lds)) != hipSuccess) return e;
   const long long nrows = (long long)p.Nx * p.Ny;
-  hipLaunchKernelGGL(k_c2r_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, F, nrows,
-                     rows, as_desc<T>(p.f_Nz), f, cfg.wave);
-  return hipGetLastError();
+  return ct_pick(CtInverse{}, p.Nz, [&](auto c) {
+    hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T, decltype(c)::value>), lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL((k_c2r_z<T, decltype(c)::value>), dim3((unsigned)((nrows + rows - 1) / rows)),
+                       dim3(cfg.threads), lds, s, F, nrows, rows, as_desc<T>(p.f_Nz), f, cfg.wave);
+    return hipGetLastError();
+  });
 }
 
 template <typename T>
 hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t s) {
   cx<T>* D = static_cast<cx<T>*>(Dh);
-  const FftCfg cfg = fft_cfg();
+  const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
   const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_r2c_z<T>), lds);
-  if (e != hipSuccess) return e;
   const long long nrows = (long long)p.Nx * p.Ny;
-  hipLaunchKernelGGL(k_r2c_z<T>, dim3((unsigned)((nrows + rows - 1) / rows)), dim3(cfg.threads), lds, s, f, nrows,
-                     rows, as_desc<T>(p.f_Nz), D);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipError_t e = ct_pick(CtInverse{}, p.Nz, [&](auto c) {
+    hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_r2c_z<T, decltype(c)::value>), lds);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL((k_r2c_z<T, decltype(c)::value>), dim3((unsigned)((nrows + rows - 1) / rows)),
+                       dim3(cfg.threads), lds, s, f, nrows, rows, as_desc<T>(p.f_Nz), D);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
   return launch_xy<T, false>(p, D, false, s);
 }
+
 
 // Batched forms of the inverse passes.
 template <typename T>

@@ -6,6 +6,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "fft_device.hpp"
@@ -36,10 +37,38 @@ constexpr int kWaveFftMax = 1024;
 
 // FFT work-group shape: 256 threads, at most 8 sequences per group (measured
 // best on MI355X among 128-512 threads and 4-16 sequences, block or wave mode)
+constexpr int kFftCap = 8;
 struct FftCfg {
-  int threads = 256, cap = 8, wave = 0;
+  int threads = 256, cap = kFftCap, wave = 0;
 };
 static inline FftCfg fft_cfg() { return FftCfg{}; }
+// The inverse 3-D FFT's x and y passes read and write the half spectrum in
+// runs of `cap` consecutive z modes: 16 per group measured faster there.
+constexpr int kInvCap = 16;
+static inline FftCfg inv_cfg() { return FftCfg{256, kInvCap, 0}; }
+
+// Lengths with compile-time FFT instantiations (fft_ct); a launcher calls
+// f(std::integral_constant<int, N>) for a listed length and
+// f(std::integral_constant<int, 0>) (the runtime plan) otherwise.
+template <int... Ns>
+struct CtList {};
+// sequences of length n a 256-thread group can hold, capped
+__host__ __device__ constexpr int ct_maxb(int n, int cap) {
+  return n > 0 && kFftMaxV * kFftThreads / n < cap ? kFftMaxV * kFftThreads / n : cap;
+}
+using CtLateral = CtList<256, 384, 512>;
+using CtInverse = CtList<128, 256, 512>;
+using CtTemporal = CtList<2048, 2560, 4096>;
+
+template <class F>
+static inline hipError_t ct_pick(CtList<>, int, F&& f) {
+  return f(std::integral_constant<int, 0>{});
+}
+template <int N0, int... Ns, class F>
+static inline hipError_t ct_pick(CtList<N0, Ns...>, int n, F&& f) {
+  if (n == N0) return f(std::integral_constant<int, N0>{});
+  return ct_pick(CtList<Ns...>{}, n, f);
+}
 
 template <typename T, bool INV>
 __device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int nseq, int bstride, int tid, int nthr,

@@ -12,7 +12,7 @@ namespace patk {
 // Stage 2: FFT along x of every grid row, keeping the Nx centred modes.
 // U[b][py][px] -> V[b][jj][py], jj = j mod Nx for j in [-Nx/2, Nx/2).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
                                            int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm, int bx, int by) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -32,7 +32,10 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
         buf[r * bstride + lpos(q - r * n_x)] = v;
       });
   __syncthreads();
-  fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nr, fd.tw, tid);
+  else
+    fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
   __syncthreads();
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
   staged_copy<kFftMaxV>(
@@ -49,10 +52,10 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
       });
 }
 
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
                                                      int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
-  fft_x_body<T>(U, n_y, Nx, rows, b_begin, fd, V, wm, blockIdx.x, blockIdx.y);
+  fft_x_body<T, NCT>(U, n_y, Nx, rows, b_begin, fd, V, wm, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -63,12 +66,15 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
   if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
       b_begin < 0 || b_end > p.nb || b_begin >= b_end)
     return hipErrorInvalidValue;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x<T>), lds);
-  if (e != hipSuccess) return e;
-  dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
-  hipLaunchKernelGGL(k_fft_x<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
-                     b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
-  return hipGetLastError();
+  auto go = [&](auto kern) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
+    hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
+                       b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
+    return hipGetLastError();
+  };
+  return ct_pick(CtLateral{}, p.n_x, [&](auto c) { return go(&k_fft_x<T, decltype(c)::value>); });
 }
 
 // ---------------------------------------------------------------------------
@@ -76,7 +82,7 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
 // transform in x and y (eq. NED_NUFFT's 1/Psi_j), and transpose so the bins
 // of each lateral mode are contiguous: V[b][jj][py] -> Gh[jj][kk][b].
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                            const T* __restrict__ dcx, const T* __restrict__ dcy,
                                            FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm, int bx, int by) {
@@ -100,7 +106,10 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
         buf[bi * bstride + lpos(q - bi * n_y)] = v;
       });
   __syncthreads();
-  fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nbc, fd.tw, tid);
+  else
+    fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
   __syncthreads();
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
@@ -120,11 +129,11 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
       });
 }
 
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                                      const T* __restrict__ dcx, const T* __restrict__ dcy,
                                                      FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
-  fft_y_body<T>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, blockIdx.x, blockIdx.y);
+  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, blockIdx.x, blockIdx.y);
 }
 
 template <typename T>
@@ -134,13 +143,16 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
   const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y<T>), lds);
-  if (e != hipSuccess) return e;
-  dim3 grid((p.nb + bins - 1) / bins, p.Nx);
-  hipLaunchKernelGGL(k_fft_y<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
-                     bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                     static_cast<cx<T>*>(Gh), cfg.wave);
-  return hipGetLastError();
+  auto go = [&](auto kern) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+    hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
+                       bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
+                       static_cast<cx<T>*>(Gh), cfg.wave);
+    return hipGetLastError();
+  };
+  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y<T, decltype(c)::value>); });
 }
 
 // ---------------------------------------------------------------------------
@@ -149,7 +161,7 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
 // inverse FFT).
 // Gh'[j][k][b] -> V'[b][j][py] = dcx_j sum_k dcy_k Gh'[j][k][b] e^{+2 pi i k py/n_y}
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict__ Gh, int nb, int Nx, int Ny,
                                                        int bins, const T* __restrict__ dcx,
                                                        const T* __restrict__ dcy, FftDesc<T> fd,
@@ -184,7 +196,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
         buf[(q - kk * nbc) * bstride + lpos(k < 0 ? k + n_y : k)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, true, false>(buf, fd, nbc, bstride, tid, nthr);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), true>(buf, nbc, fd.tw, tid);
+  else
+    fft_lds<T, kFftMaxV, true, false>(buf, fd, nbc, bstride, tid, nthr);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nbc * n_y, tid, nthr,
@@ -205,13 +220,16 @@ hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t
   const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_y_t<T>), lds);
-  if (e != hipSuccess) return e;
-  dim3 grid((p.nb + bins - 1) / bins, p.Nx);
-  hipLaunchKernelGGL(k_fft_y_t<T>, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(Gh), p.nb, p.Nx, p.Ny,
-                     bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                     static_cast<cx<T>*>(V));
-  return hipGetLastError();
+  auto go = [&](auto kern) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
+    if (e != hipSuccess) return e;
+    dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+    hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(Gh), p.nb, p.Nx, p.Ny,
+                       bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
+                       static_cast<cx<T>*>(V));
+    return hipGetLastError();
+  };
+  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y_t<T, decltype(c)::value>); });
 }
 
 // V'[b][j][py] -> U'[b - b_begin][py][px] = sum_j V'[b][j][py] e^{+2 pi i j px/n_x}

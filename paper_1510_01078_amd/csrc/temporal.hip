@@ -17,7 +17,7 @@ namespace patk {
 // ---------------------------------------------------------------------------
 constexpr int kTemporalThreads = 512;
 
-template <typename T>
+template <typename T, int NCT = 0>
 __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, int Nt, int n0,
                                               const T* __restrict__ hw, const T* __restrict__ deap,
                                               FftDesc<T> fd, int b_lo, int nb, int pairs,
@@ -53,7 +53,10 @@ __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, in
         buf[pr * L + lpos(pos)] = v;
       });
   __syncthreads();
-  fft_lds<T, kFftMaxV, false>(buf, fd, np, L, tid, nthr);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kTemporalThreads, 1, false>(buf, np, fd.tw, tid);
+  else
+    fft_lds<T, kFftMaxV, false>(buf, fd, np, L, tid, nthr);
   const FastDiv div_nb(nb);
   for (int q = tid; q < np * nb; q += nthr) {
     const int pr = div_nb(q);
@@ -70,12 +73,12 @@ __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, in
   }
 }
 
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
                                                              const T* __restrict__ hw, const T* __restrict__ deap,
                                                              FftDesc<T> fd, int b_lo, int nb, int pairs,
                                                              cx<T>* __restrict__ Gt) {
-  temporal_body<T>(g, M, Nt, n0, hw, deap, fd, b_lo, nb, pairs, Gt, blockIdx.x);
+  temporal_body<T, NCT>(g, M, Nt, n0, hw, deap, fd, b_lo, nb, pairs, Gt, blockIdx.x);
 }
 
 template <typename T>
@@ -84,12 +87,14 @@ hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted
   const int pairs = 1;  // one sensor pair per group measured fastest on MI355X
   const int blocks = (p.M + 2 * pairs - 1) / (2 * pairs);
   const size_t lds = size_t(pairs) * lseq(p.n_t) * sizeof(cx<T>);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_temporal<T>, dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M, p.Nt, p.n0,
-                     weighted ? static_cast<const T*>(p.hw) : nullptr, static_cast<const T*>(p.deap),
-                     as_desc<T>(p.f_nt), p.b_lo, p.nb, pairs, static_cast<cx<T>*>(Gt));
-  return hipGetLastError();
+  return ct_pick(CtTemporal{}, p.n_t, [&](auto c) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T, decltype(c)::value>), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_temporal<T, decltype(c)::value>), dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M,
+                       p.Nt, p.n0, weighted ? static_cast<const T*>(p.hw) : nullptr, static_cast<const T*>(p.deap),
+                       as_desc<T>(p.f_nt), p.b_lo, p.nb, pairs, static_cast<cx<T>*>(Gt));
+    return hipGetLastError();
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -101,7 +106,7 @@ hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted
 // covers a bin twice (nb <= n_t), so each of the two placement passes
 // writes distinct slots.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NCT>
 __global__ __launch_bounds__(kTemporalThreads) void k_temporal_t(const cx<T>* __restrict__ Gt, int M, int Nt, int n0,
                                                                const T* __restrict__ deap, FftDesc<T> fd, int b_lo,
                                                                int nb, T* __restrict__ g) {
@@ -131,7 +136,10 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal_t(const cx<T>* __
     z = cx<T>{z.x + T(0.5) * (a.x + c.y), z.y + T(0.5) * (c.x - a.y)};
   }
   __syncthreads();
-  fft_lds<T, kFftMaxV, true>(buf, fd, 1, lseq(n_t), tid, nthr);
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kTemporalThreads, 1, true>(buf, 1, fd.tw, tid);
+  else
+    fft_lds<T, kFftMaxV, true>(buf, fd, 1, lseq(n_t), tid, nthr);
   __syncthreads();
   for (int n = tid; n < Nt; n += nthr) {
     int pos = n - n0;
@@ -147,12 +155,14 @@ template <typename T>
 hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s) {
   if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t || p.nb > p.n_t) return hipErrorInvalidValue;
   const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal_t<T>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_temporal_t<T>, dim3((p.M + 1) / 2), dim3(kTemporalThreads), lds, s,
-                     static_cast<const cx<T>*>(Gt), p.M, p.Nt, p.n0, static_cast<const T*>(p.deap), as_desc<T>(p.f_nt),
-                     p.b_lo, p.nb, g);
-  return hipGetLastError();
+  return ct_pick(CtTemporal{}, p.n_t, [&](auto c) {
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal_t<T, decltype(c)::value>), lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_temporal_t<T, decltype(c)::value>), dim3((p.M + 1) / 2), dim3(kTemporalThreads), lds, s,
+                       static_cast<const cx<T>*>(Gt), p.M, p.Nt, p.n0, static_cast<const T*>(p.deap),
+                       as_desc<T>(p.f_nt), p.b_lo, p.nb, g);
+    return hipGetLastError();
+  });
 }
 
 // Batched form: one launch over the sensor pairs of every problem.
