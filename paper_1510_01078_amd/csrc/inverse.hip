@@ -56,7 +56,9 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
 template <typename T, bool INV, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, int Ny, int Lh, int lchunk,
                                                       FftDesc<T> fd, int wm) {
-  cfft_x_body<T, INV, NCT>(F, Ny, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+  // neighbouring groups share the 128-byte lines of the z runs: keep them on one XCD
+  const int gl = xcd_linear();
+  cfft_x_body<T, INV, NCT>(F, Ny, Lh, lchunk, fd, wm, gl % gridDim.x, gl / gridDim.x);
 }
 
 template <typename T, bool INV, int NCT = 0>
@@ -103,7 +105,9 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
 template <typename T, bool INV, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd,
                                                       int wm) {
-  cfft_y_body<T, INV, NCT>(F, Lh, lchunk, fd, wm, blockIdx.x, blockIdx.y);
+  // neighbouring groups share the 128-byte lines of the z runs: keep them on one XCD
+  const int gl = xcd_linear();
+  cfft_y_body<T, INV, NCT>(F, Lh, lchunk, fd, wm, gl % gridDim.x, gl / gridDim.x);
 }
 
 template <typename T, int NCT = 0>

@@ -160,6 +160,16 @@ __device__ __forceinline__ A batch_args(const BatchMeta<A>& m, int p) {
   return a;
 }
 
+// Linear index of this work-group in a 2-D grid with the hardware's
+// round-robin placement over the 8 XCDs undone: work-groups with consecutive
+// results run on the same XCD and share its L2 (a partial tail keeps its
+// own order).
+__device__ __forceinline__ int xcd_linear() {
+  const int b = blockIdx.x + gridDim.x * blockIdx.y;
+  const int per = int(gridDim.x * gridDim.y) / 8;
+  return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
 // Problem of batched work item w: the largest p with prefix[p] <= w.
 __device__ __forceinline__ int batch_locate(const int* prefix, int nprob, int w) {
   int lo = 0, hi = nprob - 1;

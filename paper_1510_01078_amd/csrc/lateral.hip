@@ -55,7 +55,10 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
 template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
                                                      int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
-  fft_x_body<T, NCT>(U, n_y, Nx, rows, b_begin, fd, V, wm, blockIdx.x, blockIdx.y);
+  // neighbouring groups write the two halves of each 128-byte output line:
+  // keep them on one XCD so its L2 merges the halves
+  const int gl = xcd_linear();
+  fft_x_body<T, NCT>(U, n_y, Nx, rows, b_begin, fd, V, wm, gl % gridDim.x, gl / gridDim.x);
 }
 
 template <typename T>
@@ -133,7 +136,10 @@ template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                                      const T* __restrict__ dcx, const T* __restrict__ dcy,
                                                      FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
-  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, blockIdx.x, blockIdx.y);
+  // neighbouring groups write the two halves of each 128-byte output line:
+  // keep them on one XCD so its L2 merges the halves
+  const int gl = xcd_linear();
+  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, gl % gridDim.x, gl / gridDim.x);
 }
 
 template <typename T>
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_y = fd.n;
   const int bstride = lseq(n_y);
-  const int jj = blockIdx.y;
+  const int jj = blockIdx.y;  // (an XCD-grouped order measured slower here)
   const int b0 = blockIdx.x * bins;
   const int nbc = min(bins, nb - b0);
   const int gap = n_y - Ny;  // zero slots k = Ny/2 .. n_y - Ny/2 - 1
