@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "kernels_common.hpp"
 
@@ -43,6 +44,31 @@ __device__ __forceinline__ T tap_weight(const T* __restrict__ hcoef, int t, int 
   return v;
 }
 
+// Compile-time tap count WT: the coefficients sit in LDS by degree
+// (c[d*WT + t] is the y^d coefficient of tap t), and all taps' Horner chains
+// advance together, so the multiply-adds of different taps are independent
+// and the coefficient reads are LDS broadcasts. Same operations per tap as
+// tap_weight, so the same values.
+constexpr int kMaxTapCoefs = 16 * 25;  // w_t <= 16 taps, degree <= 24
+
+template <typename T, int WT>
+__device__ __forceinline__ void stage_tap_coefs(T* c, const T* __restrict__ hcoef, int deg) {
+  for (int q = threadIdx.x; q < WT * (deg + 1); q += blockDim.x) {
+    const int t = q / (deg + 1);
+    c[(q - t * (deg + 1)) * WT + t] = hcoef[q];
+  }
+}
+
+template <typename T, int WT>
+__device__ __forceinline__ void tap_weights(const T* c, int deg, T y, T (&v)[WT]) {
+#pragma unroll
+  for (int t = 0; t < WT; ++t) v[t] = c[deg * WT + t];
+  for (int d = deg - 1; d >= 0; --d) {
+#pragma unroll
+    for (int t = 0; t < WT; ++t) v[t] = v[t] * y + c[d * WT + t];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Stage 4: temporal interpolation, one thread per (j, k, l), l = 0..Nz/2.
 //   S+(K) = exp(-2 pi i s n0/n_t) sum_t phi_t(s - b_t) Gh[j][k][b_t]
@@ -59,11 +85,15 @@ __device__ __forceinline__ T tap_weight(const T* __restrict__ hcoef, int t, int 
 // ---------------------------------------------------------------------------
 enum { MODE_IMAGE = 0, MODE_PHYSICAL = 1, MODE_ADJOINT = 2 };
 
-template <typename T, int MODE>
+// WT > 0: compile-time tap count with the coefficients staged in LDS at
+// `coefs` (stage_tap_coefs, before the call); WT = 0: runtime wt, coefficients
+// read from hcoef.
+template <typename T, int MODE, int WT = 0>
 __device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
                                             double s_per_k, double kxu, double kyu, double kzu, double two_c,
                                             double n0_over_nt, double scale, int wt, int deg,
-                                            const T* __restrict__ hcoef, cx<T>* __restrict__ Fh, int bx) {
+                                            const T* __restrict__ hcoef, cx<T>* __restrict__ Fh, int bx,
+                                            const T* coefs = nullptr) {
   const int Lh = Nz / 2 + 1;
   const long long total = (long long)Nx * Ny * Lh;
   const long long idx = (long long)bx * blockDim.x + threadIdx.x;
@@ -86,15 +116,35 @@ __device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb
   const cx<T>* src = Gh + col * nb + tp.base;
   const cx<T>* src2 = Gh + ((long long)((Nx - jj) % Nx) * Ny + (Ny - kk) % Ny) * nb + tp.base;
   cx<T> acc{T(0), T(0)}, acc2{T(0), T(0)};
-  for (int t = 0; t < wt; ++t) {
-    const T v = tap_weight(hcoef, t, deg, y);
-    const cx<T> gv = src[t];
-    acc.x += v * gv.x;
-    acc.y += v * gv.y;
-    if (MODE == MODE_ADJOINT) {
-      const cx<T> gv2 = src2[t];
-      acc2.x += v * gv2.x;
-      acc2.y += v * gv2.y;
+  if constexpr (WT > 0) {
+    cx<T> gv[WT], gv2[MODE == MODE_ADJOINT ? WT : 1];
+#pragma unroll
+    for (int t = 0; t < WT; ++t) {
+      gv[t] = src[t];
+      if (MODE == MODE_ADJOINT) gv2[t] = src2[t];
+    }
+    T v[WT];
+    tap_weights<T, WT>(coefs, deg, y, v);
+#pragma unroll
+    for (int t = 0; t < WT; ++t) {
+      acc.x += v[t] * gv[t].x;
+      acc.y += v[t] * gv[t].y;
+      if (MODE == MODE_ADJOINT) {
+        acc2.x += v[t] * gv2[t].x;
+        acc2.y += v[t] * gv2[t].y;
+      }
+    }
+  } else {
+    for (int t = 0; t < wt; ++t) {
+      const T v = tap_weight(hcoef, t, deg, y);
+      const cx<T> gv = src[t];
+      acc.x += v * gv.x;
+      acc.y += v * gv.y;
+      if (MODE == MODE_ADJOINT) {
+        const cx<T> gv2 = src2[t];
+        acc2.x += v * gv2.x;
+        acc2.y += v * gv2.y;
+      }
     }
   }
   if (MODE == MODE_ADJOINT) {
@@ -109,13 +159,32 @@ __device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb
   Fh[idx] = cmul(acc, ph);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int WT>
 __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
                                                 double s_per_k, double kxu, double kyu, double kzu, double two_c,
                                                 double n0_over_nt, double scale, int wt, int deg,
                                                 const T* __restrict__ hcoef, cx<T>* __restrict__ Fh) {
-  gather_body<T, MODE>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt, deg, hcoef, Fh,
-                       blockIdx.x);
+  __shared__ T coefs[kMaxTapCoefs];
+  stage_tap_coefs<T, WT>(coefs, hcoef, deg);
+  __syncthreads();
+  gather_body<T, MODE, WT>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt, deg, hcoef,
+                           Fh, blockIdx.x, coefs);
+}
+
+// Compile-time tap counts: every even w_t in 2..16 (the plan's range).
+template <class F>
+static hipError_t wt_pick(int wt, F&& f) {
+  switch (wt) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 4: return f(std::integral_constant<int, 4>{});
+    case 6: return f(std::integral_constant<int, 6>{});
+    case 8: return f(std::integral_constant<int, 8>{});
+    case 10: return f(std::integral_constant<int, 10>{});
+    case 12: return f(std::integral_constant<int, 12>{});
+    case 14: return f(std::integral_constant<int, 14>{});
+    case 16: return f(std::integral_constant<int, 16>{});
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T>
@@ -125,25 +194,30 @@ hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, int mode, h
   const cx<T>* in = static_cast<const cx<T>*>(Gh);
   cx<T>* out = static_cast<cx<T>*>(Fh);
   const T* hc = static_cast<const T*>(p.hcoef);
-  switch (mode) {
-    case GATHER_IMAGE:
-      hipLaunchKernelGGL((k_gather<T, MODE_IMAGE>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
-                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.inv_vol, p.w_t, p.hdeg, hc,
-                         out);
-      break;
-    case GATHER_PHYSICAL:
-      hipLaunchKernelGGL((k_gather<T, MODE_PHYSICAL>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
-                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, 1.0, p.w_t, p.hdeg, hc, out);
-      break;
-    case GATHER_ADJOINT:
-      hipLaunchKernelGGL((k_gather<T, MODE_ADJOINT>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx, p.Ny,
-                         p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.adj_scale, p.w_t, p.hdeg,
-                         hc, out);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (p.w_t * (p.hdeg + 1) > kMaxTapCoefs) return hipErrorInvalidValue;
+  return wt_pick(p.w_t, [&](auto c) {
+    constexpr int WT = decltype(c)::value;
+    switch (mode) {
+      case GATHER_IMAGE:
+        hipLaunchKernelGGL((k_gather<T, MODE_IMAGE, WT>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx,
+                           p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.inv_vol, p.w_t, p.hdeg,
+                           hc, out);
+        break;
+      case GATHER_PHYSICAL:
+        hipLaunchKernelGGL((k_gather<T, MODE_PHYSICAL, WT>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx,
+                           p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, 1.0, p.w_t, p.hdeg, hc,
+                           out);
+        break;
+      case GATHER_ADJOINT:
+        hipLaunchKernelGGL((k_gather<T, MODE_ADJOINT, WT>), dim3(blocks), dim3(256), 0, s, in, p.nb, p.b_lo, p.Nx,
+                           p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, p.adj_scale, p.w_t,
+                           p.hdeg, hc, out);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -162,20 +236,24 @@ hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, int mode, h
 // atomic-free. A work-group handles a few consecutive columns so that the
 // per-l phase keeps its threads busy.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, int nb, int b_lo, int Nx, int Ny, int Nz,
                                                  double s_per_k, double kxu, double kyu, double kzu, double n0_over_nt,
                                                  double scale, int deriv, int wt, int deg, const T* __restrict__ hcoef,
-                                                 int cols_per_group, cx<T>* __restrict__ Gh) {
+                                                 int cols_per_group, int first_table, cx<T>* __restrict__ Gh) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* coefs = reinterpret_cast<T*>(smem_raw);  // [kMaxTapCoefs] tap coefficients by degree
+  stage_tap_coefs<T, WT>(coefs, hcoef, deg);
+  __syncthreads();
   const int Lz = Nz / 2;
   const int Lh = Lz + 1;
   const int ncol_total = Nx * Ny;
   const int col0 = blockIdx.x * cols_per_group;
   const int ncol = min(cols_per_group, ncol_total - col0);
-  cx<T>* s_z = reinterpret_cast<cx<T>*>(smem_raw);                  // [ncol][Lz]
+  cx<T>* s_z = reinterpret_cast<cx<T>*>(coefs + kMaxTapCoefs);      // [ncol][Lz]
   T* s_w = reinterpret_cast<T*>(s_z + cols_per_group * Lz);          // [ncol][Lz][wt]
   int* s_base = reinterpret_cast<int*>(s_w + cols_per_group * Lz * wt);  // [ncol][Lz]
+  int* s_first = s_base + cols_per_group * Lz;  // [ncol][nb] first contributing l per bin (when first_table)
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int q = tid; q < ncol * Lz; q += nthr) {
     const int ci = q / Lz;
@@ -188,7 +266,12 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, i
     const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
     const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
     const T y = T(tp.y);
-    for (int t = 0; t < wt; ++t) s_w[q * wt + t] = tap_weight(hcoef, t, deg, y);
+    {
+      T v[WT];
+      tap_weights<T, WT>(coefs, deg, y, v);
+#pragma unroll
+      for (int t = 0; t < WT; ++t) s_w[q * WT + t] = v[t];
+    }
     s_base[q] = tp.base;
     cx<T> z{T(0), T(0)};
     if (jj != Nx / 2 && kk != Ny / 2) {
@@ -203,15 +286,34 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, i
     s_z[q] = z;
   }
   __syncthreads();
+  if (first_table) {
+    // the bases are non-decreasing in l, so the first l whose taps reach bin
+    // b (base_l + wt - 1 >= b) is l for the bins in
+    // (base_{l-1} + wt - 1, base_l + wt - 1]; bins below base_0 or past
+    // base_{Lz-1} + wt - 1 get no contribution and are not tabulated
+    for (int q = tid; q < ncol * Lz; q += nthr) {
+      const int ci = q / Lz;
+      const int l = q - ci * Lz;
+      const int* base = s_base + ci * Lz;
+      const int b0 = l == 0 ? base[0] : base[l - 1] + wt;
+      const int b1 = min(nb - 1, base[l] + wt - 1);
+      for (int b = b0; b <= b1; ++b) s_first[ci * nb + b] = l;
+    }
+    __syncthreads();
+  }
   for (int q = tid; q < ncol * nb; q += nthr) {
     const int ci = q / nb;
     const int b = q - ci * nb;
     const int* base = s_base + ci * Lz;
     // contributions come from the l with base_l in [b - wt + 1, b]
     int lo = 0, hi = Lz;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (base[mid] < b - wt + 1) lo = mid + 1; else hi = mid;
+    if (first_table) {
+      lo = b < base[0] || b > base[Lz - 1] + wt - 1 ? Lz : s_first[q];
+    } else {
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] < b - wt + 1) lo = mid + 1; else hi = mid;
+      }
     }
     cx<T> acc{T(0), T(0)};
     for (int l = lo; l < Lz && base[l] <= b; ++l) {
@@ -232,25 +334,37 @@ static int scatter_cols(const DevPlan& p) {
   return c < 1 ? 1 : (c > 8 ? 8 : c);
 }
 
+// per-bin table of first contributions in LDS when it takes at most 16 KiB
+// (else a binary search over the bases per bin)
+template <typename T>
+static bool scatter_first_table(const DevPlan& p) {
+  return size_t(scatter_cols<T>(p)) * p.nb * sizeof(int) <= 16384;
+}
+
 template <typename T>
 size_t scatter_lds_bytes(const DevPlan& p) {
   const size_t Lz = size_t(p.Nz / 2) * scatter_cols<T>(p);
-  return Lz * sizeof(cx<T>) + Lz * p.w_t * sizeof(T) + Lz * sizeof(int);
+  const size_t first = scatter_first_table<T>(p) ? size_t(scatter_cols<T>(p)) * p.nb * sizeof(int) : 0;
+  return kMaxTapCoefs * sizeof(T) + Lz * sizeof(cx<T>) + Lz * p.w_t * sizeof(T) + Lz * sizeof(int) + first;
 }
 
 template <typename T>
 hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv, hipStream_t s) {
   if (deriv < 0 || deriv > 2) return hipErrorInvalidValue;
   const size_t lds = scatter_lds_bytes<T>(p);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_scatter<T>), lds);
+  if (p.w_t * (p.hdeg + 1) > kMaxTapCoefs) return hipErrorInvalidValue;
+  return wt_pick(p.w_t, [&](auto c) {
+  constexpr int WT = decltype(c)::value;
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_scatter<T, WT>), lds);
   if (e != hipSuccess) return e;
   const int cpg = scatter_cols<T>(p);
   const int ncol = p.Nx * p.Ny;
-  hipLaunchKernelGGL(k_scatter<T>, dim3((unsigned)((ncol + cpg - 1) / cpg)), dim3(256), lds, s,
+  hipLaunchKernelGGL((k_scatter<T, WT>), dim3((unsigned)((ncol + cpg - 1) / cpg)), dim3(256), lds, s,
                      static_cast<const cx<T>*>(Dh), p.nb, p.b_lo, p.Nx, p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu,
                      p.n0_over_nt, p.adj_scale, deriv, p.w_t, p.hdeg, static_cast<const T*>(p.hcoef), cpg,
-                     static_cast<cx<T>*>(Gh));
+                     scatter_first_table<T>(p) ? 1 : 0, static_cast<cx<T>*>(Gh));
   return hipGetLastError();
+  });
 }
 
 // Batched form of the reconstruction's interpolation (image-ready spectrum).
