@@ -187,6 +187,11 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
   }
   unsigned char* tb = static_cast<unsigned char*>(G.tables);
   const bool kahan = B->plans[0]->dp.kahan;
+  int wt = G.members.empty() ? 0 : B->plans[G.members[0]]->dp.w_t;
+  for (int m : G.members) {
+    const patk::DevPlan& d = B->plans[m]->dp;
+    if (d.w_t != wt || d.w_t * (d.hdeg + 1) > patk::kMaxTapCoefs) wt = 0;
+  }
   for (int i = 0; i < kStages; ++i) {
     G.st[i].args = tb + oa[i];
     G.st[i].prefix = reinterpret_cast<const int*>(tb + op[i]);
@@ -195,6 +200,7 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     G.st[i].lds = lds[i];
     G.st[i].grid = kPersistentBlocks;
     G.st[i].kahan = kahan;
+    G.st[i].wt = wt;
   }
   return PAT_OK;
 }

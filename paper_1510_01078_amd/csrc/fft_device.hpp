@@ -260,8 +260,10 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int bat
 // ---------------------------------------------------------------------------
 // Compile-time form for one length N: the same passes (radices taken greedily
 // in the order 8, 4, 2, 5, 3, as the host planner does), twiddle reads and
-// butterflies as fft_lds with the host plan for N, so the results are the
-// same; with N, the radix, p and the butterfly count known to the compiler,
+// butterflies as fft_lds with the host plan for N (the compiler may fuse
+// multiplies and adds differently in the two forms, so results agree to
+// rounding, and bit for bit where it does not); with N, the radix, p and the
+// butterfly count known to the compiler,
 // the index arithmetic folds to constants and the LDS offsets of a
 // butterfly's R inputs and outputs become instruction immediates where the
 // pad pattern allows (strides that are multiples of 8 slots). Sequences sit

@@ -48,8 +48,8 @@ __device__ __forceinline__ T tap_weight(const T* __restrict__ hcoef, int t, int 
 // (c[d*WT + t] is the y^d coefficient of tap t), and all taps' Horner chains
 // advance together, so the multiply-adds of different taps are independent
 // and the coefficient reads are LDS broadcasts. Same operations per tap as
-// tap_weight, so the same values.
-constexpr int kMaxTapCoefs = 16 * 25;  // w_t <= 16 taps, degree <= 24
+// tap_weight (the batched gather's form); the batch tests check that both
+// give the same bits.
 
 template <typename T, int WT>
 __device__ __forceinline__ void stage_tap_coefs(T* c, const T* __restrict__ hcoef, int deg) {
@@ -368,17 +368,29 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
 }
 
 // Batched form of the reconstruction's interpolation (image-ready spectrum).
-template <typename T>
+// WT > 0: every problem of the group has WT taps; a work-group restages the
+// tap coefficients in LDS when its next work item belongs to another problem.
+template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict__ args, const int* __restrict__ prefix,
                              int nprob, int total, BatchIO io) {
   __shared__ BatchMeta<GatherBA> meta;
+  __shared__ T coefs[WT > 0 ? kMaxTapCoefs : 1];
   batch_meta_load(meta, args, prefix, nprob);
+  int staged = -1;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const GatherBA a = batch_args(meta, p);
-    gather_body<T, MODE_IMAGE>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k, a.kxu, a.kyu,
-                               a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg, static_cast<const T*>(a.hcoef),
-                               static_cast<cx<T>*>(a.Fh), w - meta.prefix[p]);
+    if constexpr (WT > 0) {
+      if (p != staged) {
+        stage_tap_coefs<T, WT>(coefs, static_cast<const T*>(a.hcoef), a.deg);
+        __syncthreads();
+        staged = p;
+      }
+    }
+    gather_body<T, MODE_IMAGE, WT>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k, a.kxu,
+                                   a.kyu, a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg,
+                                   static_cast<const T*>(a.hcoef), static_cast<cx<T>*>(a.Fh), w - meta.prefix[p],
+                                   coefs);
     __syncthreads();
   }
 }
@@ -386,11 +398,16 @@ __global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict
 template <typename T>
 hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
   if (st.total <= 0) return hipSuccess;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T>), st.lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_gather_batch<T>), dim3(batch_grid(st)), dim3(256), st.lds, s,
-                     static_cast<const GatherBA*>(st.args), st.prefix, st.nprob, st.total, io);
-  return hipGetLastError();
+  auto go = [&](auto c) {
+    constexpr int WT = decltype(c)::value;
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T, WT>), st.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_gather_batch<T, WT>), dim3(batch_grid(st)), dim3(256), st.lds, s,
+                       static_cast<const GatherBA*>(st.args), st.prefix, st.nprob, st.total, io);
+    return hipGetLastError();
+  };
+  if (st.wt == 0) return go(std::integral_constant<int, 0>{});
+  return wt_pick(st.wt, go);
 }
 
 #define PATK_INST(T)                                                                     \

@@ -127,9 +127,9 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 // (W-1)-row halo of V' (periodic in y), embeds the Nx kept modes of every row
 // into n_x slots, inverse-FFTs the rows in LDS (one wave per row), then
 // interpolates every sensor whose footprint origin lies in the strip straight
-// from LDS. Per sensor the footprint sum runs in the same order as k_interp,
-// and the row transforms are those of k_fft_x_t, so both forms give the same
-// bits.
+// from LDS. Per sensor the footprint sum runs in the same order as k_interp
+// and the row transforms take the same passes as k_fft_x_t, so the two forms
+// agree to rounding.
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 512;
 

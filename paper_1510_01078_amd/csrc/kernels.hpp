@@ -183,7 +183,11 @@ struct BatchStage {
   size_t lds = 0;
   int grid = 0;
   bool kahan = false;  // spread with compensated summation
+  int wt = 0;          // temporal taps shared by every problem of the group (0: they differ)
 };
+
+// temporal tap polynomials staged in LDS: at most 16 taps of degree <= 24
+constexpr int kMaxTapCoefs = 16 * 25;
 
 template <typename T> hipError_t launch_temporal_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 template <typename T> hipError_t launch_spread_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
