@@ -35,9 +35,12 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
         const int jj = div_nl(q);
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
+  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
   else
     fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
@@ -84,9 +87,12 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
         const int kk = div_nl(q);
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
+  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
   else
     fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
   __syncthreads();
@@ -130,9 +136,12 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
         buf[r * bstride + lpos(l)] = v;
         if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
       });
+  cx<T>* twl = buf + rows * bstride;
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nr, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nr, twl, tid);
   else
     fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
   __syncthreads();
@@ -171,9 +180,12 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
         const int r = div_nz(q);
         buf[r * bstride + lpos(q - r * Nz)] = cx<T>{v, T(0)};
       });
+  cx<T>* twl = buf + rows * bstride;
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), false>(buf, nr, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), false>(buf, nr, twl, tid);
   else
     fft_lds<T, kFftMaxV, false, false>(buf, fd, nr, bstride, tid, nthr);
   __syncthreads();
@@ -196,7 +208,7 @@ static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_
     hipError_t e;
     if (along_x) {
       const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
-      const size_t lds = size_t(lc) * lseq(p.Nx) * sizeof(cx<T>);
+      const size_t lds = (size_t(lc) * lseq(p.Nx) + p.Nx) * sizeof(cx<T>);
       e = ct_pick(CtInverse{}, p.Nx, [&](auto c) {
         const void* kern = reinterpret_cast<const void*>(&k_cfft_x<T, INV, decltype(c)::value>);
         hipError_t e2 = allow_lds(kern, lds);
@@ -208,7 +220,7 @@ static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_
       });
     } else {
       const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
-      const size_t lds = size_t(lc) * lseq(p.Ny) * sizeof(cx<T>);
+      const size_t lds = (size_t(lc) * lseq(p.Ny) + p.Ny) * sizeof(cx<T>);
       e = ct_pick(CtInverse{}, p.Ny, [&](auto c) {
         const void* kern = reinterpret_cast<const void*>(&k_cfft_y<T, INV, decltype(c)::value>);
         hipError_t e2 = allow_lds(kern, lds);
@@ -231,7 +243,7 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
   if (e != hipSuccess) return e;
   const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
-  const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+  const size_t lds = (size_t(rows) * lseq(p.Nz) + p.Nz) * sizeof(cx<T>);
   const long long nrows = (long long)p.Nx * p.Ny;
   return ct_pick(CtInverse{}, p.Nz, [&](auto c) {
     hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T, decltype(c)::value>), lds);
@@ -247,7 +259,7 @@ hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t 
   cx<T>* D = static_cast<cx<T>*>(Dh);
   const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
-  const size_t lds = size_t(rows) * lseq(p.Nz) * sizeof(cx<T>);
+  const size_t lds = (size_t(rows) * lseq(p.Nz) + p.Nz) * sizeof(cx<T>);
   const long long nrows = (long long)p.Nx * p.Ny;
   hipError_t e = ct_pick(CtInverse{}, p.Nz, [&](auto c) {
     hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_r2c_z<T, decltype(c)::value>), lds);

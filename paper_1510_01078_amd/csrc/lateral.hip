@@ -31,9 +31,13 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
         const int r = div_nx(q);
         buf[r * bstride + lpos(q - r * n_x)] = v;
       });
+  // compile-time form: the twiddles go to LDS behind the rows (every pass reads them)
+  cx<T>* twl = buf + rows * bstride;
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nr, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nr, twl, tid);
   else
     fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
   __syncthreads();
@@ -65,7 +69,7 @@ template <typename T>
 hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, int b_end, hipStream_t s) {
   const FftCfg cfg = fft_cfg();
   const int rows = fft_batch<T>(p.n_x, cfg.threads, cfg.cap);
-  const size_t lds = size_t(rows) * lseq(p.n_x) * sizeof(cx<T>);
+  const size_t lds = (size_t(rows) * lseq(p.n_x) + p.n_x) * sizeof(cx<T>);
   if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
       b_begin < 0 || b_end > p.nb || b_begin >= b_end)
     return hipErrorInvalidValue;
@@ -108,9 +112,12 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
         const int bi = div_ny(q);
         buf[bi * bstride + lpos(q - bi * n_y)] = v;
       });
+  cx<T>* twl = buf + bins * bstride;
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nbc, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nbc, twl, tid);
   else
     fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
   __syncthreads();
@@ -146,7 +153,7 @@ template <typename T>
 hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s) {
   const FftCfg cfg = fft_cfg();
   const int bins = fft_batch<T>(p.n_y, cfg.threads, cfg.cap);
-  const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  const size_t lds = (size_t(bins) * lseq(p.n_y) + p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
   auto go = [&](auto kern) {
@@ -201,9 +208,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
         const int k = kk < Ny / 2 ? kk : kk - Ny;
         buf[(q - kk * nbc) * bstride + lpos(k < 0 ? k + n_y : k)] = v;
       });
+  cx<T>* twl = buf + bins * bstride;
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), true>(buf, nbc, fd.tw, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), true>(buf, nbc, twl, tid);
   else
     fft_lds<T, kFftMaxV, true, false>(buf, fd, nbc, bstride, tid, nthr);
   __syncthreads();
@@ -223,7 +233,7 @@ template <typename T>
 hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t s) {
   const FftCfg cfg = fft_cfg();
   const int bins = fft_batch<T>(p.n_y, cfg.threads, cfg.cap);
-  const size_t lds = size_t(bins) * lseq(p.n_y) * sizeof(cx<T>);
+  const size_t lds = (size_t(bins) * lseq(p.n_y) + p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
   auto go = [&](auto kern) {
