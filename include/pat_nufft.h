@@ -119,7 +119,8 @@ typedef struct pat_plan pat_plan;
 
 /* Sizes the plan derived; filled by pat_plan_get_info. */
 typedef struct pat_plan_info {
-  int32_t nx_over, ny_over;  /* oversampled lateral grid */
+  int32_t nx_over, ny_over;  /* oversampled lateral grid: the smallest even 2,3,5-smooth lengths
+                                >= max(sigma_xy * n, width_xy) */
   int32_t nt_over;           /* oversampled temporal FFT length */
   int32_t band_lo;           /* first oversampled temporal bin kept (may be < 0) */
   int32_t band_bins;         /* number of temporal bins kept */

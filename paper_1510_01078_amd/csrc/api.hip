@@ -137,8 +137,11 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.Nx = d.nx;
   dp.Ny = d.ny;
   dp.Nz = d.nz;
-  dp.n_x = next_smooth_even(d.sigma_xy * d.nx);
-  dp.n_y = next_smooth_even(d.sigma_xy * d.ny);
+  // an oversampled lateral axis holds at least one window footprint, so a
+  // footprint meets every grid point at most once (short axes get a larger
+  // effective oversampling; the deconvolution uses the actual length)
+  dp.n_x = next_smooth_even(std::max(d.sigma_xy * d.nx, double(d.width_xy)));
+  dp.n_y = next_smooth_even(std::max(d.sigma_xy * d.ny, double(d.width_xy)));
   const bool linear_t = d.temporal_interp == PAT_INTERP_LINEAR;
   dp.n_t = next_smooth_even(d.sigma_t * Nt);
   // band of oversampled temporal bins the interpolation reads: |K| from 0 (the
@@ -408,6 +411,9 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
   P->forward_ok = patk::scatter_lds_bytes<T>(dp) <= (size_t)lds_limit;
   P->forward_fused = patk::fused_interp_ok<T>(dp, (size_t)lds_limit);
+  // two home-tile rows per fused strip (32 + w - 1 grid rows for 32: less
+  // halo recomputation, measured faster) where the work-group LDS holds them
+  dp.fused_strip = dp.tiles_y >= 2 && patk::fused_interp_lds<T>(dp, 2) <= (size_t)lds_limit ? 2 : 1;
   const size_t szA = align_up(std::max(sz_U, sz_Gh));
   const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;

@@ -122,8 +122,9 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 
 // ---------------------------------------------------------------------------
 // Fused form of k_fft_x_t followed by k_interp: the oversampled grid U' never
-// goes to memory. A work-group owns one strip of kSpreadTile grid rows (a row
-// of home tiles) and a run of bins. Per bin it loads the strip's rows plus a
+// goes to memory. A work-group owns one strip of FS*kSpreadTile grid rows (FS
+// rows of home tiles; two where the LDS holds them, with 1024 threads, else
+// one with 512) and a run of bins. Per bin it loads the strip's rows plus a
 // (W-1)-row halo of V' (periodic in y), embeds the Nx kept modes of every row
 // into n_x slots, inverse-FFTs the rows in LDS (one wave per row), then
 // interpolates every sensor whose footprint origin lies in the strip straight
@@ -131,14 +132,11 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 // and the row transforms take the same passes as k_fft_x_t, so the two forms
 // agree to rounding.
 // ---------------------------------------------------------------------------
-constexpr int kFusedThreads = 512;
+constexpr int kFusedThreads = 512;  // per home-tile row of the strip
 
-template <int W>
-__host__ __device__ constexpr int fused_rows() { return kSpreadTile + W - 1; }
+template <int W, int FS>
+__host__ __device__ constexpr int fused_rows() { return FS * kSpreadTile + W - 1; }
 
-// Sensors a thread keeps in registers across the bins of its work-group
-// (footprint origin, columns and weights); sensors of a strip beyond
-// kFusedKeep * kFusedThreads are reloaded per bin.
 // One sensor of the strip: footprint origin row within the strip, the LDS
 // slots of its footprint columns, and its weights.
 template <typename T, int W>
@@ -185,22 +183,23 @@ __device__ __forceinline__ cx<T> fused_sensor_sum(const FusedSensor<T, W>& f, co
   return acc;
 }
 
-template <typename T, int W, int MAXV, int NCT>
-__global__ __launch_bounds__(kFusedThreads) void k_fft_x_interp(
+template <typename T, int W, int MAXV, int NCT, int FS>
+__global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
     const cx<T>* __restrict__ V, int nb, int Nx, int n_y, int tiles_x, int nchunks, int bins,
     const int* __restrict__ home_off, const int* __restrict__ home_sens, const int* __restrict__ sbx,
     const int* __restrict__ sby, const T* __restrict__ swx, const T* __restrict__ swy, FftDesc<T> fd,
     cx<T>* __restrict__ Gt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  constexpr int R = fused_rows<W>();
+  constexpr int R = fused_rows<W, FS>();
   const int chunk = blockIdx.x % nchunks;  // bins vary fastest: neighbouring groups share the strip's sensors
   const int strip = blockIdx.x / nchunks;
-  const int q0 = home_off[strip * tiles_x], q1 = home_off[(strip + 1) * tiles_x];
+  const int tiles_y = (n_y + kSpreadTile - 1) / kSpreadTile;
+  const int q0 = home_off[strip * FS * tiles_x], q1 = home_off[min(strip * FS + FS, tiles_y) * tiles_x];
   if (q0 == q1) return;
   const int n_x = fd.n;
   const int bstride = lseq(n_x);
-  const int py0 = strip * kSpreadTile;
+  const int py0 = strip * FS * kSpreadTile;
   const int b0 = chunk * bins, b1 = min(nb, b0 + bins);
   const int gap = n_x - Nx;
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -255,31 +254,38 @@ __global__ __launch_bounds__(kFusedThreads) void k_fft_x_interp(
 }
 
 template <typename T>
-size_t fused_interp_lds(const DevPlan& p) {
-  return size_t(kSpreadTile + p.w_xy - 1) * lseq(p.n_x) * sizeof(cx<T>);
+size_t fused_interp_lds(const DevPlan& p, int strip_tiles) {
+  return size_t(strip_tiles * kSpreadTile + p.w_xy - 1) * lseq(p.n_x) * sizeof(cx<T>);
 }
 
 template <typename T>
 bool fused_interp_ok(const DevPlan& p, size_t lds_limit) {
   return p.n_x <= kWaveFftMax && p.w_xy >= 2 && p.w_xy <= 16 && (p.w_xy % 2) == 0 && p.Nx <= p.n_x &&
-         fused_interp_lds<T>(p) <= lds_limit;
+         fused_interp_lds<T>(p, 1) <= lds_limit;
 }
 
-template <typename T, int W, int MAXV, int NCT>
-static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
-  const size_t lds = fused_interp_lds<T>(p);
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_interp<T, W, MAXV, NCT>), lds);
+template <typename T, int W, int MAXV, int NCT, int FS>
+static hipError_t launch_fused_wvs(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
+  const size_t lds = fused_interp_lds<T>(p, FS);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_fft_x_interp<T, W, MAXV, NCT, FS>), lds);
   if (e != hipSuccess) return e;
   // bins per work-group: enough groups to fill the device several times over
-  const long long strips = p.tiles_y;
-  int bins = int(std::min<long long>(8, std::max<long long>(1, strips * p.nb / 2048)));
+  const long long strips = (p.tiles_y + FS - 1) / FS;
+  int bins = int(std::min<long long>(8, std::max<long long>(1, p.tiles_y * p.nb / 2048)));
   const int nchunks = (p.nb + bins - 1) / bins;
   const long long blocks = strips * nchunks;
-  hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV, NCT>), dim3((unsigned)blocks), dim3(kFusedThreads), lds, s,
+  hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV, NCT, FS>), dim3((unsigned)blocks), dim3(kFusedThreads * FS), lds, s,
                      static_cast<const cx<T>*>(V), p.nb, p.Nx, p.n_y, p.tiles_x, nchunks, bins, p.home_off,
                      p.home_sens, p.sbx, p.sby, static_cast<const T*>(p.swx), static_cast<const T*>(p.swy),
                      as_desc<T>(p.f_nx), static_cast<cx<T>*>(Gt));
   return hipGetLastError();
+}
+
+// strip height chosen by the plan (DevPlan::fused_strip)
+template <typename T, int W, int MAXV, int NCT>
+static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
+  if (p.fused_strip == 2) return launch_fused_wvs<T, W, MAXV, NCT, 2>(p, V, Gt, s);
+  return launch_fused_wvs<T, W, MAXV, NCT, 1>(p, V, Gt, s);
 }
 
 // rows of up to 512 points need 8 values per lane in the one-wave transform, longer ones 16
@@ -312,7 +318,7 @@ hipError_t launch_fft_x_interp(const DevPlan& p, const void* V, void* Gt, hipStr
 
 #define PATK_INST(T) template hipError_t launch_interp<T>(const DevPlan&, const void*, void*, int, int, hipStream_t); \
   template hipError_t launch_fft_x_interp<T>(const DevPlan&, const void*, void*, hipStream_t);                   \
-  template size_t fused_interp_lds<T>(const DevPlan&);                                                        \
+  template size_t fused_interp_lds<T>(const DevPlan&, int);                                                        \
   template bool fused_interp_ok<T>(const DevPlan&, size_t);
 PATK_INST(float)
 PATK_INST(double)

@@ -58,6 +58,7 @@ struct DevPlan {
   int patches_y = 0;
   const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
   const int* home_sens = nullptr; // [M]
+  int fused_strip = 1;            // home-tile rows per strip of the fused forward kernel (1 or 2)
   const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
   const void* dcy = nullptr;      // [Ny]
   const void* hcoef = nullptr;    // [w_t][hdeg+1] temporal tap polynomials
@@ -117,8 +118,9 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 // work-group LDS limit.
 template <typename T>
 hipError_t launch_fft_x_interp(const DevPlan& p, const void* V, void* Gt, hipStream_t s);
+// LDS of the fused kernel for a strip of strip_tiles rows of home tiles
 template <typename T>
-size_t fused_interp_lds(const DevPlan& p);
+size_t fused_interp_lds(const DevPlan& p, int strip_tiles);
 template <typename T>
 bool fused_interp_ok(const DevPlan& p, size_t lds_limit);
 // Gt' -> g[m][n] (unit weights)
