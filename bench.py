@@ -155,6 +155,31 @@ def recorded_traffic(args, band_bins):
     return None
 
 
+def fp64_compare(args, p, g, dev):
+    """The plain FP64 form (same kernels instantiated with double, same window
+    setting) on the same traces: time per reconstruction, and the relative L2
+    difference between the FP32 and FP64 images."""
+    import torch
+    from paper_1510_01078_amd import Plan
+    settings = dict(kernel=args.kernel, sigma_xy=args.sigma_xy, width_xy=args.width_xy, sigma_t=args.sigma_t,
+                    width_t=args.width_t)
+    p32 = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision=args.precision, device=dev,
+               **settings)
+    f32 = p32.reconstruct(g).double()
+    p32.close()
+    p64 = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp64", device=dev, **settings)
+    g64 = g.double()
+    out64 = torch.empty(p.shape, dtype=torch.float64, device=dev)
+    steps = max(1, min(args.steps, 10))
+    ms = _time_calls(lambda: p64.reconstruct(g64, out=out64), steps, max(1, args.warmup), dev)
+    rel = float(torch.linalg.vector_norm(f32 - out64) / torch.linalg.vector_norm(out64))
+    p64.close()
+    voxels = float(np.prod(p.shape))
+    log(f"fp64 plain form: {ms:.4f} ms per step; FP32 vs FP64 image rel-L2 {rel:.3e}")
+    return {"ms_per_step": round(ms, 5), "value": voxels / (ms * 1e-3), "unit": "voxels/s", "steps": steps,
+            "fp32_vs_fp64_rel_l2": rel}
+
+
 def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
     """Time the FP64 oracle on `nsample` lateral x-modes (all y-modes, all
     depths), extrapolate to the full grid (plus the full inverse transform),
@@ -220,6 +245,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8, help="lateral x-modes in the oracle sample")
     ap.add_argument("--batch", choices=["on", "off"], default="on",
                     help="also time the 32-problem batched reconstruction against sequential plans")
+    ap.add_argument("--fp64-compare", choices=["on", "off"], default="on",
+                    help="also time the plain FP64 form on the same workload and compare its image with FP32's")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB of one plain device-to-device copy run before the timed loop (scales HBM counters)")
     args = ap.parse_args()
@@ -333,6 +360,9 @@ def main():
                      "stages_ms": {n: round(v / max(1, nc), 5) for n, v in zip(snames, sm)}}
         log(f"{name}: {ops[name]['ms_per_call']:.4f} ms per call")
     result["operators"] = ops
+
+    if args.fp64_compare == "on" and args.precision != "fp64":
+        result["fp64_plain"] = fp64_compare(args, p, g, dev)
 
     if args.batch == "on":
         result["batch"] = bench_batch(args, dev)
