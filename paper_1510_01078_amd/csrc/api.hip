@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kernels_common.hpp"
 #include "pat_nufft.h"
 #include "plan_internal.hpp"
 #include "window.hpp"
@@ -346,6 +347,53 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   }
   dp.hdeg = deg;
   const size_t o_hc = add_real<T>(blob, coef);
+  // per x-mode range of band bins the interpolation reads (reconstruction,
+  // adjoint, spectrum): modes (j, k, l) with |k| <= Ny/2, l <= Nz/2 read bins
+  // base(s) .. base(s) + w_t - 1 with s = |K| s_per_k non-decreasing in |k| and
+  // l, so x-mode j needs base(s(j,0,0)) .. base(s(j,Ny/2,Nz/2)) + w_t - 1; one
+  // bin of margin on each side (host and device may round |K| apart), widened
+  // to whole groups of the y-FFT's bins. The y-FFT skips the rest (skipping
+  // the x-FFT's writes there measured slower: the stores lose their full lines).
+  std::vector<int> jr(2 * size_t(d.nx));
+  {
+    const int ybins = patk::fft_batch<T>(dp.n_y, patk::kFftThreads, patk::kFftCap);
+    const int wt = dp.w_t;
+    auto base = [&](double sv) {
+      long b = (long)std::floor(sv) - wt / 2 + 1 - dp.b_lo;
+      return (int)std::min<long>(std::max<long>(b, 0), dp.nb - wt);
+    };
+    const double Ky = (d.ny / 2) * dp.kyu, Kz = (d.nz / 2) * dp.kzu;
+    for (int jj = 0; jj < d.nx; ++jj) {
+      const int j = jj < d.nx / 2 ? jj : jj - d.nx;
+      const double Kx = j * dp.kxu;
+      int lo = std::max(0, base(std::fabs(Kx) * dp.s_per_k) - 1);
+      int hi = std::min(dp.nb - 1, base(std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz) * dp.s_per_k) + wt);
+      lo = lo / ybins * ybins;
+      hi = std::min(dp.nb - 1, hi / ybins * ybins + ybins - 1);
+      jr[2 * jj] = lo;
+      jr[2 * jj + 1] = hi;
+    }
+  }
+  const size_t o_jr = blob.add(jr.data(), jr.size() * sizeof(int));
+  // the same ranges per bin: both ends are non-decreasing in |j|, so the
+  // x-modes that hold bin b are J0(b) <= |j| <= J1(b) (J0 > J1: none)
+  std::vector<int> br(2 * size_t(dp.nb));
+  {
+    const int half = d.nx / 2;
+    for (int b = 0; b < dp.nb; ++b) {
+      int j0 = half + 1, j1 = -1;
+      for (int aj = 0; aj <= half; ++aj) {
+        const int jj = aj < half ? aj : half;  // |j| = Nx/2 is the mode jj = Nx/2
+        if (jr[2 * jj] <= b && b <= jr[2 * jj + 1]) {
+          j0 = std::min(j0, aj);
+          j1 = std::max(j1, aj);
+        }
+      }
+      br[2 * b] = j0;
+      br[2 * b + 1] = j1;
+    }
+  }
+  const size_t o_br = blob.add(br.data(), br.size() * sizeof(int));
   // twiddles
   const size_t o_tw_nt = add_twiddles<T>(blob, dp.n_t);
   const size_t o_tw_nx = add_twiddles<T>(blob, dp.n_x);
@@ -381,6 +429,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.dcx = at(o_dcx);
   dp.dcy = at(o_dcy);
   dp.hcoef = at(o_hc);
+  dp.jrange = static_cast<const int*>(at(o_jr));
+  dp.brange = static_cast<const int*>(at(o_br));
   dp.f_nt.tw = at(o_tw_nt);
   dp.f_nx.tw = at(o_tw_nx);
   dp.f_ny.tw = at(o_tw_ny);
@@ -484,7 +534,13 @@ pat_status run_traces_in(pat_plan* P, const void* g, void* out, void* ws, hipStr
 // stage index of the stage each kernel transposes.
 template <typename T>
 pat_status run_image_in(pat_plan* P, const void* f, void* g, void* ws, hipStream_t s, Op op) {
-  const patk::DevPlan& dp = P->dp;
+  // the band ranges prune the forward path only with the fused kernel (the
+  // two-kernel form reads every x-mode of every bin)
+  patk::DevPlan dp = P->dp;
+  if (!P->forward_fused) {
+    dp.jrange = nullptr;
+    dp.brange = nullptr;
+  }
   unsigned char* A = static_cast<unsigned char*>(ws);
   unsigned char* B = A + P->off_B;
   unsigned char* C = A + P->off_C;

@@ -240,7 +240,8 @@ template <typename T, int WT>
 __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, int nb, int b_lo, int Nx, int Ny, int Nz,
                                                  double s_per_k, double kxu, double kyu, double kzu, double n0_over_nt,
                                                  double scale, int deriv, int wt, int deg, const T* __restrict__ hcoef,
-                                                 int cols_per_group, int first_table, cx<T>* __restrict__ Gh) {
+                                                 int cols_per_group, int first_table, const int* __restrict__ jrange,
+                                                 cx<T>* __restrict__ Gh) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* coefs = reinterpret_cast<T*>(smem_raw);  // [kMaxTapCoefs] tap coefficients by degree
   stage_tap_coefs<T, WT>(coefs, hcoef, deg);
@@ -301,14 +302,34 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, i
     }
     __syncthreads();
   }
-  for (int q = tid; q < ncol * nb; q += nthr) {
-    const int ci = q / nb;
-    const int b = q - ci * nb;
+  // bins written per column: the x-mode's range (the transposed y-FFT skips
+  // the rest, which get no contribution), else the whole band
+  __shared__ int s_run[2 * 8];
+  if (tid < ncol) {
+    int lo = 0, hi = nb - 1;
+    if (jrange) {
+      const int jj = (col0 + tid) / Ny;
+      lo = jrange[2 * jj];
+      hi = jrange[2 * jj + 1];
+    }
+    s_run[2 * tid] = lo;
+    s_run[2 * tid + 1] = hi >= lo ? hi - lo + 1 : 0;
+  }
+  __syncthreads();
+  int total = 0;
+  for (int ci = 0; ci < ncol; ++ci) total += s_run[2 * ci + 1];
+  for (int q = tid; q < total; q += nthr) {
+    int ci = 0, rq = q;
+    while (rq >= s_run[2 * ci + 1]) {
+      rq -= s_run[2 * ci + 1];
+      ++ci;
+    }
+    const int b = s_run[2 * ci] + rq;
     const int* base = s_base + ci * Lz;
     // contributions come from the l with base_l in [b - wt + 1, b]
     int lo = 0, hi = Lz;
     if (first_table) {
-      lo = b < base[0] || b > base[Lz - 1] + wt - 1 ? Lz : s_first[q];
+      lo = b < base[0] || b > base[Lz - 1] + wt - 1 ? Lz : s_first[ci * nb + b];
     } else {
       while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -362,7 +383,7 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
   hipLaunchKernelGGL((k_scatter<T, WT>), dim3((unsigned)((ncol + cpg - 1) / cpg)), dim3(256), lds, s,
                      static_cast<const cx<T>*>(Dh), p.nb, p.b_lo, p.Nx, p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu,
                      p.n0_over_nt, p.adj_scale, deriv, p.w_t, p.hdeg, static_cast<const T*>(p.hcoef), cpg,
-                     scatter_first_table<T>(p) ? 1 : 0, static_cast<cx<T>*>(Gh));
+                     scatter_first_table<T>(p) ? 1 : 0, p.jrange, static_cast<cx<T>*>(Gh));
   return hipGetLastError();
   });
 }

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
     const cx<T>* __restrict__ V, int nb, int Nx, int n_y, int tiles_x, int nchunks, int bins,
     const int* __restrict__ home_off, const int* __restrict__ home_sens, const int* __restrict__ sbx,
     const int* __restrict__ sby, const T* __restrict__ swx, const T* __restrict__ swy, FftDesc<T> fd,
-    cx<T>* __restrict__ Gt) {
+    const int* __restrict__ brange, cx<T>* __restrict__ Gt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   constexpr int R = fused_rows<W, FS>();
@@ -207,34 +207,42 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
   const FastDiv div_gap(gap > 0 ? gap : 1), div_r(R);
   const size_t plane = size_t(Nx) * n_y;
   const int total = R * Nx;
+  // grid row of each strip row (periodic in y; short axes wrap more than once)
+  __shared__ int s_row[R];
+  for (int r = tid; r < R; r += nthr) s_row[r] = (py0 + r) % n_y;
   for (int b = b0; b < b1; ++b) {
     for (int q = tid; q < R * gap; q += nthr) {
       const int r = div_gap(q);
       buf[r * bstride + lpos(Nx / 2 + (q - r * gap))] = cx<T>{T(0), T(0)};
     }
-    // element q of the strip: mode jj = q / R of grid row py0 + q mod R (periodic in y)
+    // element q of the strip: mode jj = q / R of grid row py0 + q mod R (periodic
+    // in y); x-modes outside [J0, J1] for this bin are zero (not written)
     const cx<T>* src = V + size_t(b) * plane;
+    const int J0 = brange ? brange[2 * b] : 0, J1 = brange ? brange[2 * b + 1] : Nx;
     constexpr int kStage = 8;
     for (int qs = 0; qs < total; qs += kStage * nthr) {
       cx<T> v[kStage];
       int dst[kStage];
+      bool ok[kStage];
+      // every lane loads (lanes outside the window all read element 0, one
+      // line), so the loads stay in flight together; zeros are chosen at the store
 #pragma unroll
       for (int u = 0; u < kStage; ++u) {
         const int q = qs + tid + u * nthr;
-        dst[u] = -1;
-        if (q < total) {
-          const int jj = div_r(q);
-          const int r = q - jj * R;
-          int py = py0 + r;
-          while (py >= n_y) py -= n_y;
-          v[u] = src[size_t(jj) * n_y + py];
-          const int j = jj < Nx / 2 ? jj : jj - Nx;
-          dst[u] = r * bstride + lpos(j < 0 ? j + n_x : j);
-        }
+        const bool in = q < total;
+        const int qc = in ? q : 0;  // straight-line code: the loads stay back to back
+        const int jj = div_r(qc);
+        const int r = qc - jj * R;
+        const int py = s_row[r];
+        const int j = jj < Nx / 2 ? jj : jj - Nx;
+        const int aj = j < 0 ? -j : j;
+        ok[u] = in && aj >= J0 && aj <= J1;
+        v[u] = src[ok[u] ? size_t(jj) * n_y + py : 0];
+        dst[u] = in ? r * bstride + lpos(j < 0 ? j + n_x : j) : -1;
       }
 #pragma unroll
       for (int u = 0; u < kStage; ++u)
-        if (dst[u] >= 0) buf[dst[u]] = v[u];
+        if (dst[u] >= 0) buf[dst[u]] = ok[u] ? v[u] : cx<T>{T(0), T(0)};
     }
     __syncthreads();
     for (int r = wave; r < R; r += nwaves) {
@@ -277,7 +285,7 @@ static hipError_t launch_fused_wvs(const DevPlan& p, const void* V, void* Gt, hi
   hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV, NCT, FS>), dim3((unsigned)blocks), dim3(kFusedThreads * FS), lds, s,
                      static_cast<const cx<T>*>(V), p.nb, p.Nx, p.n_y, p.tiles_x, nchunks, bins, p.home_off,
                      p.home_sens, p.sbx, p.sby, static_cast<const T*>(p.swx), static_cast<const T*>(p.swy),
-                     as_desc<T>(p.f_nx), static_cast<cx<T>*>(Gt));
+                     as_desc<T>(p.f_nx), p.brange, static_cast<cx<T>*>(Gt));
   return hipGetLastError();
 }
 

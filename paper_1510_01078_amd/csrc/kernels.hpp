@@ -59,6 +59,9 @@ struct DevPlan {
   const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
   const int* home_sens = nullptr; // [M]
   int fused_strip = 1;            // home-tile rows per strip of the fused forward kernel (1 or 2)
+  const int* jrange = nullptr;    // [Nx][2] first and last band bin the interpolation reads per x-mode,
+                                  // in whole groups of the y-FFT's bins; the y-FFT skips the others
+  const int* brange = nullptr;    // [nb][2] per band bin the smallest and largest |j| whose range holds it
   const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
   const void* dcy = nullptr;      // [Ny]
   const void* hcoef = nullptr;    // [w_t][hdeg+1] temporal tap polynomials

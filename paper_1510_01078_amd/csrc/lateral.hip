@@ -89,10 +89,13 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
 // transform in x and y (eq. NED_NUFFT's 1/Psi_j), and transpose so the bins
 // of each lateral mode are contiguous: V[b][jj][py] -> Gh[jj][kk][b].
 // ---------------------------------------------------------------------------
+// jrange (may be nullptr): groups of bins outside the x-mode's range are
+// skipped (the interpolation never reads them).
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                            const T* __restrict__ dcx, const T* __restrict__ dcy,
-                                           FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm, int bx, int by) {
+                                           FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm, int bx, int by,
+                                           const int* __restrict__ jrange = nullptr) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -101,6 +104,7 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
   const int jj = by;
   const int b0 = bx * bins;
   const int nbc = min(bins, nb - b0);
+  if (jrange && (b0 + nbc - 1 < jrange[2 * jj] || b0 > jrange[2 * jj + 1])) return;
   const FastDiv div_ny(n_y), div_nbc(nbc);
   staged_copy<kFftMaxV>(
       nbc * n_y, tid, nthr,
@@ -142,11 +146,12 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
 template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                                      const T* __restrict__ dcx, const T* __restrict__ dcy,
-                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm) {
+                                                     FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm,
+                                                     const int* __restrict__ jrange) {
   // neighbouring groups write the two halves of each 128-byte output line:
   // keep them on one XCD so its L2 merges the halves
   const int gl = xcd_linear();
-  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, gl % gridDim.x, gl / gridDim.x);
+  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, gl % gridDim.x, gl / gridDim.x, jrange);
 }
 
 template <typename T>
@@ -162,7 +167,7 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
     dim3 grid((p.nb + bins - 1) / bins, p.Nx);
     hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
                        bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                       static_cast<cx<T>*>(Gh), cfg.wave);
+                       static_cast<cx<T>*>(Gh), cfg.wave, p.jrange);
     return hipGetLastError();
   };
   return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y<T, decltype(c)::value>); });
@@ -178,7 +183,7 @@ template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict__ Gh, int nb, int Nx, int Ny,
                                                        int bins, const T* __restrict__ dcx,
                                                        const T* __restrict__ dcy, FftDesc<T> fd,
-                                                       cx<T>* __restrict__ V) {
+                                                       cx<T>* __restrict__ V, const int* __restrict__ jrange) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
@@ -187,6 +192,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
   const int jj = blockIdx.y;  // (an XCD-grouped order measured slower here)
   const int b0 = blockIdx.x * bins;
   const int nbc = min(bins, nb - b0);
+  // bins outside the x-mode's range hold zeros that nothing reads: skipped
+  if (jrange && (b0 + nbc - 1 < jrange[2 * jj] || b0 > jrange[2 * jj + 1])) return;
   const int gap = n_y - Ny;  // zero slots k = Ny/2 .. n_y - Ny/2 - 1
   const FastDiv div_gap(gap), div_nbc(nbc), div_ny(n_y);
   for (int q = tid; q < nbc * gap; q += nthr) {
@@ -242,7 +249,7 @@ hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t
     dim3 grid((p.nb + bins - 1) / bins, p.Nx);
     hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(Gh), p.nb, p.Nx, p.Ny,
                        bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                       static_cast<cx<T>*>(V));
+                       static_cast<cx<T>*>(V), p.jrange);
     return hipGetLastError();
   };
   return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y_t<T, decltype(c)::value>); });
