@@ -459,11 +459,12 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t sz_V = size_t(dp.nb) * d.nx * dp.n_y * c;
   const size_t sz_Gh = size_t(d.nx) * d.ny * dp.nb * c;
   const size_t sz_F = size_t(d.nx) * d.ny * (d.nz / 2 + 1) * c;
-  P->forward_ok = patk::scatter_lds_bytes<T>(dp) <= (size_t)lds_limit;
-  P->forward_fused = patk::fused_interp_ok<T>(dp, (size_t)lds_limit);
+  P->forward_ok = patk::scatter_lds_bytes<T>(dp) + patk::kStaticLdsMargin <= (size_t)lds_limit;
+  P->forward_fused = patk::fused_interp_ok<T>(dp, (size_t)lds_limit - patk::kStaticLdsMargin);
   // two home-tile rows per fused strip (32 + w - 1 grid rows for 32: less
   // halo recomputation, measured faster) where the work-group LDS holds them
-  dp.fused_strip = dp.tiles_y >= 2 && patk::fused_interp_lds<T>(dp, 2) <= (size_t)lds_limit ? 2 : 1;
+  dp.fused_strip =
+      dp.tiles_y >= 2 && patk::fused_interp_lds<T>(dp, 2) + patk::kStaticLdsMargin <= (size_t)lds_limit ? 2 : 1;
   const size_t szA = align_up(std::max(sz_U, sz_Gh));
   const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;

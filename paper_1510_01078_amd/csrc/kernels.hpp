@@ -121,6 +121,10 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 // work-group LDS limit.
 template <typename T>
 hipError_t launch_fft_x_interp(const DevPlan& p, const void* V, void* Gt, hipStream_t s);
+// Static LDS that the fused kernel and the transposed interpolation hold
+// beside their dynamic LDS (row and run tables); the plan's fit checks add it.
+constexpr size_t kStaticLdsMargin = 512;
+
 // LDS of the fused kernel for a strip of strip_tiles rows of home tiles
 template <typename T>
 size_t fused_interp_lds(const DevPlan& p, int strip_tiles);
