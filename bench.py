@@ -42,14 +42,16 @@ def log(*a):
 
 def spread_bytes(plan, p, eb):
     """Algorithmic bytes of one spread launch: read the per-sensor band values,
-    write the oversampled grid once, read the sensor tables and tile lists."""
+    write the oversampled grid once, read the packed slot tables once (per
+    slot: 64 lane weights, 64 one-byte sensor places, 4 sensor ids) and the
+    patch offsets."""
     info = plan.info
     nb, nxo, nyo = info["band_bins"], info["nx_over"], info["ny_over"]
-    w = plan._desc.width_xy
     m = p.m
     read_bins = m * nb * 2 * eb
     write_grid = nb * nxo * nyo * 2 * eb
-    tables = m * (2 * w * eb + 2 * 4) + 4 * (info["spread_tiles"] + 1) + 4 * info["spread_pairs"]
+    patches = -(-nxo // 16) * -(-nyo // 4)
+    tables = info["spread_slots"] * (64 * (eb + 1) + 4 * 4) + 4 * (patches + 1)
     return read_bins + write_grid + tables
 
 
@@ -310,7 +312,7 @@ def main():
     achieved = spread_bytes_launch / (spread_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args, plan.info["band_bins"]),
-                "kernel": "k_spread_wave",
+                "kernel": "k_spread_slots",
                 "bytes_per_launch": int(spread_bytes_launch), "ms_per_launch": round(spread_ms, 5),
                 "launches_per_step": rounds}
 

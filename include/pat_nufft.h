@@ -126,8 +126,8 @@ typedef struct pat_plan_info {
   int32_t band_bins;         /* number of temporal bins kept */
   int32_t time_origin;       /* centring offset n0 = Nt/2 of the temporal window */
   int32_t element_bytes;     /* 4 or 8 */
-  int32_t spread_tiles;      /* lateral spread tiles */
-  int64_t spread_pairs;      /* (sensor, tile) incidences in the spread lists */
+  int32_t spread_tiles;      /* 16 x 16 tiles of the oversampled lateral grid */
+  int64_t spread_pairs;      /* (sensor, patch) incidences: footprints meeting each 16 x 4 patch */
   size_t workspace_bytes;
   size_t table_bytes;        /* device bytes owned by the plan */
   int32_t chunk_bins;        /* temporal bins per spread / x-FFT round */
@@ -138,6 +138,9 @@ typedef struct pat_plan_info {
                                 kernel with no grid buffer (oversampled x length <= 1024 and a strip of
                                 16 + width_xy - 1 grid rows fits the work-group LDS); 0: two kernels in
                                 rounds of chunk_bins bins */
+  int32_t pad0;
+  int64_t spread_slots;      /* packed slots of the single-problem spread: groups of up to 4 sensors whose
+                                footprints share no point of a 16 x 4 patch of the oversampled grid */
 } pat_plan_info;
 
 /* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, window

@@ -73,6 +73,8 @@ class PlanInfo(C.Structure):
         ("deconv_range_xy", C.c_double),
         ("deconv_range_t", C.c_double),
         ("forward_fused", C.c_int32),
+        ("pad0", C.c_int32),
+        ("spread_slots", C.c_int64),
     ]
 
 

@@ -233,36 +233,11 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t o_sby = blob.add(sby.data(), sby.size() * sizeof(int));
   const size_t o_swx = add_real<T>(blob, swx);
   const size_t o_swy = add_real<T>(blob, swy);
-  // tile lists: sensors whose (periodic) footprint meets each 16x16 tile, in sensor order
+  // 16 x 16 tiles of the oversampled grid (the forward model's home lists)
   const int TS = patk::kSpreadTile;
   dp.tiles_x = (dp.n_x + TS - 1) / TS;
   dp.tiles_y = (dp.n_y + TS - 1) / TS;
   const int ntiles = dp.tiles_x * dp.tiles_y;
-  std::vector<int> cnt(ntiles + 1, 0);
-  std::vector<std::pair<int, int>> inc;
-  inc.reserve(size_t(M) * 4);
-  for (int m = 0; m < M; ++m) {
-    int txs[4], tys[4], ntx = 0, nty = 0;
-    for (int t = 0; t < w; ++t) {
-      const int tx = ((sbx[m] + t) % dp.n_x) / TS;
-      if (std::find(txs, txs + ntx, tx) == txs + ntx) txs[ntx++] = tx;
-      const int ty = ((sby[m] + t) % dp.n_y) / TS;
-      if (std::find(tys, tys + nty, ty) == tys + nty) tys[nty++] = ty;
-      if (ntx > 3 || nty > 3) break;
-    }
-    for (int a = 0; a < ntx; ++a)
-      for (int b = 0; b < nty; ++b) inc.emplace_back(tys[b] * dp.tiles_x + txs[a], m);
-  }
-  for (auto& e : inc) cnt[e.first + 1]++;
-  for (int i = 0; i < ntiles; ++i) cnt[i + 1] += cnt[i];
-  std::vector<int> sens(inc.size());
-  {
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    for (auto& e : inc) sens[pos[e.first]++] = e.second;  // stable: sensors ascending per tile
-  }
-  P->spread_pairs = (int64_t)inc.size();
-  const size_t o_toff = blob.add(cnt.data(), cnt.size() * sizeof(int));
-  const size_t o_tsens = blob.add(sens.data(), std::max<size_t>(1, sens.size()) * sizeof(int));
   // wave-patch lists: sensors whose footprint meets each 16 x kPatchRows patch
   // (a tile column and a group of rows), ascending per patch
   const int PR = patk::kPatchRows;
@@ -282,6 +257,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
     for (int a = 0; a < ntx; ++a)
       for (int b = 0; b < nrg; ++b) pinc.emplace_back(rgs[b] * dp.tiles_x + txs[a], m);
   }
+  P->spread_pairs = (int64_t)pinc.size();
   for (auto& e : pinc) pcnt[e.first + 1]++;
   for (int i = 0; i < npatch; ++i) pcnt[i + 1] += pcnt[i];
   std::vector<int> psens(pinc.size());
@@ -289,8 +265,58 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
     std::vector<int> pos(pcnt.begin(), pcnt.end() - 1);
     for (auto& e : pinc) psens[pos[e.first]++] = e.second;  // stable: sensors ascending per patch
   }
-  const size_t o_poff = blob.add(pcnt.data(), pcnt.size() * sizeof(int));
-  const size_t o_psens = blob.add(psens.data(), std::max<size_t>(1, psens.size()) * sizeof(int));
+  // packed slots of each patch: the patch's sensors (in list order) placed
+  // first-fit into slots of up to kSlotK sensors whose footprints share no
+  // grid point of the patch, with every lane's weight wx*wy and the index of
+  // the slot's sensor that covers it (weight 0 and index 0 where none does)
+  constexpr int SK = patk::kSlotK;
+  std::vector<int> soff(npatch + 1, 0), ssens;
+  std::vector<double> sw;
+  std::vector<unsigned char> sk;
+  for (int pt = 0; pt < npatch; ++pt) {
+    const int px0 = (pt % dp.tiles_x) * TS, py0 = (pt / dp.tiles_x) * PR;
+    const size_t first = ssens.size() / SK;
+    std::vector<uint64_t> used;
+    std::vector<int> fill;
+    for (int q = pcnt[pt]; q < pcnt[pt + 1]; ++q) {
+      const int m = psens[q];
+      uint64_t mask = 0;
+      for (int lane = 0; lane < 64; ++lane) {
+        const int px = px0 + (lane & 15), py = py0 + (lane >> 4);
+        if (px >= dp.n_x || py >= dp.n_y) continue;
+        const int tx = ((px - sbx[m]) % dp.n_x + dp.n_x) % dp.n_x;
+        const int ty = ((py - sby[m]) % dp.n_y + dp.n_y) % dp.n_y;
+        if (tx < w && ty < w) mask |= uint64_t(1) << lane;
+      }
+      if (!mask) continue;
+      size_t sl = 0;
+      while (sl < used.size() && (fill[sl] == SK || (used[sl] & mask))) ++sl;
+      if (sl == used.size()) {
+        used.push_back(0);
+        fill.push_back(0);
+        ssens.insert(ssens.end(), SK, -1);
+        sw.insert(sw.end(), 64, 0.0);
+        sk.insert(sk.end(), 64, 0);
+      }
+      const size_t gs = first + sl;
+      const int k = fill[sl]++;
+      used[sl] |= mask;
+      ssens[gs * SK + k] = m;
+      for (int lane = 0; lane < 64; ++lane) {
+        if (!((mask >> lane) & 1)) continue;
+        const int tx = ((px0 + (lane & 15) - sbx[m]) % dp.n_x + dp.n_x) % dp.n_x;
+        const int ty = ((py0 + (lane >> 4) - sby[m]) % dp.n_y + dp.n_y) % dp.n_y;
+        sw[gs * 64 + lane] = swx[size_t(m) * w + tx] * swy[size_t(m) * w + ty];
+        sk[gs * 64 + lane] = (unsigned char)k;
+      }
+    }
+    soff[pt + 1] = int(ssens.size() / SK);
+  }
+  P->spread_slots = (int64_t)(ssens.size() / SK);
+  const size_t o_soff = blob.add(soff.data(), soff.size() * sizeof(int));
+  const size_t o_ssens = blob.add(ssens.data(), std::max<size_t>(1, ssens.size()) * sizeof(int));
+  const size_t o_sw = add_real<T>(blob, sw.empty() ? std::vector<double>(1, 0.0) : sw);
+  const size_t o_sk = blob.add(sk.data(), std::max<size_t>(1, sk.size()));
   // home lists for the interpolation to the sensors: each sensor once, in
   // the tile holding its footprint origin, sensors ascending per tile
   std::vector<int> hcnt(ntiles + 1, 0), home(M);
@@ -420,10 +446,10 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.sby = static_cast<const int*>(at(o_sby));
   dp.swx = at(o_swx);
   dp.swy = at(o_swy);
-  dp.tile_off = static_cast<const int*>(at(o_toff));
-  dp.tile_sens = static_cast<const int*>(at(o_tsens));
-  dp.patch_off = static_cast<const int*>(at(o_poff));
-  dp.patch_sens = static_cast<const int*>(at(o_psens));
+  dp.slot_off = static_cast<const int*>(at(o_soff));
+  dp.slot_sens = static_cast<const int*>(at(o_ssens));
+  dp.slot_w = at(o_sw);
+  dp.slot_k = static_cast<const unsigned char*>(at(o_sk));
   dp.home_off = static_cast<const int*>(at(o_hoff));
   dp.home_sens = static_cast<const int*>(at(o_hsens));
   dp.dcx = at(o_dcx);
@@ -676,6 +702,8 @@ pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
   info->deconv_range_xy = P->range_xy;
   info->deconv_range_t = P->range_t;
   info->forward_fused = P->forward_fused ? 1 : 0;
+  info->pad0 = 0;
+  info->spread_slots = P->spread_slots;
   return PAT_OK;
 }
 

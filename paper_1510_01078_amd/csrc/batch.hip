@@ -120,9 +120,8 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     lds[0] = std::max(lds[0], size_t(patk::lseq(d.n_t)) * c);
     // stage 1: spread, all bins in one round
     const int nchunks = (d.nb + 15) / 16;
-    a1[p] = patk::SpreadBA{C, d.tile_off, d.tile_sens, d.sbx, d.sby, d.swx, d.swy, d.nb, d.w_xy,
-                           d.n_x, d.n_y, d.tiles_x, nchunks, A};
-    pre[1][p + 1] = d.tiles_x * d.tiles_y * nchunks;
+    a1[p] = patk::SpreadBA{C, d.slot_off, d.slot_sens, d.slot_w, d.slot_k, d.nb, d.n_x, d.n_y, d.tiles_x, nchunks, A};
+    pre[1][p + 1] = d.tiles_x * d.patches_y * ((nchunks + patk::kSpreadGroups - 1) / patk::kSpreadGroups);
     // stage 2: FFT along x
     const int rows = patk::fft_batch<T>(d.n_x, cfg.threads, cfg.cap);
     if (rows * d.n_x > kFft || rows * d.Nx > kFft) return PAT_ERR_UNSUPPORTED;

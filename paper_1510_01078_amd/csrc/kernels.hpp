@@ -51,10 +51,10 @@ struct DevPlan {
   const int* sby = nullptr;       // [M]
   const void* swx = nullptr;      // [M][w] x weights
   const void* swy = nullptr;      // [M][w]
-  const int* tile_off = nullptr;  // [tiles+1]
-  const int* tile_sens = nullptr; // sensors whose footprint meets each tile
-  const int* patch_off = nullptr; // [tiles_x*patches_y+1] sensors meeting each 16 x kPatchRows patch (CSR)
-  const int* patch_sens = nullptr;
+  const int* slot_off = nullptr;  // [tiles_x*patches_y+1] packed slots of each 16 x kPatchRows patch (CSR)
+  const int* slot_sens = nullptr; // [slots][kSlotK] sensor ids of each slot, -1 for an empty place
+  const void* slot_w = nullptr;   // [slots][64] each lane's weight wx*wy (0 where no sensor covers it)
+  const unsigned char* slot_k = nullptr;  // [slots][64] the place in the slot of the lane's sensor
   int patches_y = 0;
   const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
   const int* home_sens = nullptr; // [M]
@@ -70,6 +70,8 @@ struct DevPlan {
 
 constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
 constexpr int kPatchRows = 4;    // rows of the spread's one-wave patch (16 x 4 grid points)
+constexpr int kSlotK = 4;        // sensors per packed spread slot
+constexpr int kSpreadGroups = 2; // spread bin groups (16 bins each) per work-group
 
 // Stage launchers; T = float or double. Buffers are device pointers.
 //
@@ -160,8 +162,8 @@ struct TemporalBA {
   const void* hw; const void* deap; FftView fd; int M, Nt, n0, b_lo, nb; void* Gt;
 };
 struct SpreadBA {
-  const void* Gt; const int* tile_off; const int* tile_sens; const int* sbx; const int* sby;
-  const void* swx; const void* swy; int nb, w, n_x, n_y, tiles_x, nchunks; void* U;
+  const void* Gt; const int* slot_off; const int* slot_sens; const void* slot_w; const unsigned char* slot_k;
+  int nb, n_x, n_y, tiles_x, nchunks; void* U;
 };
 struct FftXBA {
   const void* U; FftView fd; int n_y, Nx, rows, gx; void* V;

@@ -65,6 +65,7 @@ struct pat_plan {
   size_t off_C = 0;     // B at off_B (x rows / spectrum), C at off_C (per-sensor bins)
   size_t ws_bytes = 0;
   int64_t spread_pairs = 0;
+  int64_t spread_slots = 0;
   bool forward_ok = false;  // the forward model's per-column LDS fits the device
   bool forward_fused = false;  // the forward model's x-FFT and interpolation run as one kernel
   double range_xy = 1.0;    // dynamic range of the lateral deconvolution (x times y)

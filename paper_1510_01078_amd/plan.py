@@ -114,7 +114,7 @@ class Plan:
         self._handle = handle
         info = N.PlanInfo()
         N.check(self._lib.pat_plan_get_info(handle, C.byref(info)), "pat_plan_get_info")
-        self.info = {f: getattr(info, f) for f, _ in N.PlanInfo._fields_}
+        self.info = {f: getattr(info, f) for f, _ in N.PlanInfo._fields_ if not f.startswith("pad")}
         self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=dev)
 
     # ------------------------------------------------------------------
