@@ -44,30 +44,36 @@ __device__ __forceinline__ void accum(cx<T>& a, cx<T>& c, T wt, cx<T> g) {
 // the warped 128 x 128 layout over a 384^2 grid). The plan also stores every
 // lane's weight wx*wy and which of the slot's sensors it reads, so the inner
 // loop is the LDS row reads and the FMAs. The bin values of a round's slots
-// are staged through LDS rows padded by 16 bytes, which puts the rows of one
-// slot in different banks. Each grid point sums its sensors in slot order
+// go from global memory straight into LDS (16-byte loads to LDS, no staging
+// registers), laid out load-major: load i of lane L lands at i*1024 + 16*L,
+// which puts the up to four rows of one slot in different banks. A load
+// starting past the band's last bin is moved onto that bin (its bins are
+// never stored); one starting on it may read 8 bytes past the row, which the
+// band-value buffer's 16-byte tail keeps in bounds for the last sensor. Each
+// grid point sums its sensors in slot order
 // (deterministic). A work-group takes kSpreadGroups consecutive bin groups of
 // its patch, so a patch with one round of slots (the usual case) reads its
 // lane tables once. Measured on MI355X at the headline size: 8 slots per
 // round beat 16; two bin groups per work-group beat one, four and nine;
 // splitting a group's bins over two or four passes (fewer live accumulators)
 // and XCD-contiguous or patch-major block orders were slower.
-constexpr int kSlotBatch = 8;  // slots staged per round
 
 template <typename T, bool KAHAN>
 __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, int nb,
                                                  const int* __restrict__ slot_off,
                                                  const int* __restrict__ slot_sens, const T* __restrict__ slot_w,
-                                                 const unsigned char* __restrict__ slot_k, int n_x, int n_y,
+                                                 const unsigned short* __restrict__ slot_k, int n_x, int n_y,
                                                  int tiles_x, int nchunks, int b_begin, int b_end,
                                                  cx<T>* __restrict__ U, int bx) {
   constexpr int BC = kSpreadBins, K = kSlotK, SB = kSlotBatch;
-  constexpr int RS = BC + 16 / int(sizeof(cx<T>));  // row padded by 16 bytes (elements)
   constexpr int ROWS = SB * K;
   constexpr int LPR = 64 / ROWS;  // lanes staging one row
   constexpr int EPL = BC / LPR;   // bins staged per lane
-  static_assert(64 % ROWS == 0 && BC % LPR == 0 && (RS * sizeof(cx<T>)) % 16 == 0, "staging layout");
-  __shared__ cx<T> s_g[ROWS * RS];
+  constexpr int EL = 16 / int(sizeof(cx<T>));  // bins per 16-byte load
+  constexpr int NLD = EPL / EL;                  // loads per lane per round
+  constexpr int LSTRIDE = 64 * EL;               // elements between two loads' blocks
+  static_assert(ROWS * LPR == 64 && BC % LPR == 0 && EPL % EL == 0 && SB * 2 <= 16 && K <= 4, "staging layout");
+  __shared__ __align__(16) cx<T> s_g[NLD * LSTRIDE];
   const int ngroups = (nchunks + kSpreadGroups - 1) / kSpreadGroups;
   const int grp = bx % ngroups;  // bin groups vary fastest: neighbours share the patch's slots
   const int patch = bx / ngroups;
@@ -81,7 +87,7 @@ __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, i
   const bool one_round = q_end - q_begin <= SB;
   const int row = lane / LPR, part = lane - (lane / LPR) * LPR;
   T wq[SB];
-  unsigned char kq[SB];
+  unsigned kq = 0;  // 2-bit places of the round's slots
   const int c_first = grp * kSpreadGroups;
   const int c_end = min(nchunks, c_first + kSpreadGroups);
   for (int c = c_first; c < c_end; ++c) {
@@ -99,29 +105,32 @@ __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, i
         // lane tables, read unconditionally (slots past the round's end
         // repeat its last one and go unused), so no load waits on a branch
 #pragma unroll
-        for (int q = 0; q < SB; ++q) {
-          const size_t at = size_t(qb + min(q, nq - 1)) * 64 + lane;
-          wq[q] = slot_w[at];
-          kq[q] = slot_k[at];
-        }
+        for (int q = 0; q < SB; ++q) wq[q] = slot_w[size_t(qb + min(q, nq - 1)) * 64 + lane];
+        kq = slot_k[size_t(qb) * 64 + lane];
       }
+      // an empty place loads sensor 0's row: no lane reads it
       const int rq = min(row / K, nq - 1);
-      const int sid = row / K < nq ? slot_sens[size_t(qb + rq) * K + (row - (row / K) * K)] : -1;
-      cx<T> vg[EPL];
-      const cx<T>* gs = Gt + size_t(sid < 0 ? 0 : sid) * nb + b0 + part * EPL;
-#pragma unroll
-      for (int e = 0; e < EPL; ++e) vg[e] = sid >= 0 && part * EPL + e < nbc ? gs[e] : cx<T>{T(0), T(0)};
+      const int sid = row / K < nq ? max(0, slot_sens[size_t(qb + rq) * K + (row - (row / K) * K)]) : 0;
+      const cx<T>* gs = Gt + size_t(sid) * nb;
       __syncthreads();  // the previous round has been consumed
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) s_g[row * RS + part * EPL + e] = vg[e];
+      for (int i = 0; i < NLD; ++i) {
+        const int e = min(b0 + part * EPL + i * EL, nb - 1);
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(gs + e),
+                                         (__attribute__((address_space(3))) void*)(s_g + i * LSTRIDE), 16, 0, 0);
+      }
+      __builtin_amdgcn_s_waitcnt(0);  // the loads have landed in LDS
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < SB; ++q) {
         if (q < nq) {
-          const cx<T>* gq = s_g + (q * K + int(kq[q])) * RS;
+          // bin b of row r: load (b % EPL) / EL, lane 2r + b / EPL, element b % EL
+          const cx<T>* gq = s_g + (2 * (q * K + int((kq >> (2 * q)) & 3u))) * EL;
           const T wt = wq[q];
 #pragma unroll
-          for (int b = 0; b < BC; ++b) accum<T, KAHAN>(acc[b], cmp[KAHAN ? b : 0], wt, gq[b]);
+          for (int b = 0; b < BC; ++b)
+            accum<T, KAHAN>(acc[b], cmp[KAHAN ? b : 0], wt,
+                            gq[((b % EPL) / EL) * LSTRIDE + (b / EPL) * EL + b % EL]);
         }
       }
     }
@@ -140,7 +149,7 @@ __global__ __launch_bounds__(64) void k_spread_slots(const cx<T>* __restrict__ G
                                                      const int* __restrict__ slot_off,
                                                      const int* __restrict__ slot_sens,
                                                      const T* __restrict__ slot_w,
-                                                     const unsigned char* __restrict__ slot_k, int n_x, int n_y,
+                                                     const unsigned short* __restrict__ slot_k, int n_x, int n_y,
                                                      int tiles_x, int nchunks, int b_begin, int b_end,
                                                      cx<T>* __restrict__ U) {
   spread_slot_body<T, KAHAN>(Gt, nb, slot_off, slot_sens, slot_w, slot_k, n_x, n_y, tiles_x, nchunks, b_begin,
