@@ -314,20 +314,20 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   }
   // per slot and lane, the places of the kSlotBatch slots from it on within
   // its patch, two bits each: a round reads one word per lane
-  std::vector<unsigned short> sk16(sk.size(), 0);
+  std::vector<unsigned> sk16(sk.size(), 0);
   for (int pt = 0; pt < npatch; ++pt)
     for (int q = soff[pt]; q < soff[pt + 1]; ++q)
       for (int lane = 0; lane < 64; ++lane) {
         unsigned v = 0;
         for (int i = 0; i < patk::kSlotBatch && q + i < soff[pt + 1]; ++i)
           v |= unsigned(sk[size_t(q + i) * 64 + lane]) << (2 * i);
-        sk16[size_t(q) * 64 + lane] = (unsigned short)v;
+        sk16[size_t(q) * 64 + lane] = v;
       }
   P->spread_slots = (int64_t)(ssens.size() / SK);
   const size_t o_soff = blob.add(soff.data(), soff.size() * sizeof(int));
   const size_t o_ssens = blob.add(ssens.data(), std::max<size_t>(1, ssens.size()) * sizeof(int));
   const size_t o_sw = add_real<T>(blob, sw.empty() ? std::vector<double>(1, 0.0) : sw);
-  const size_t o_sk = blob.add(sk16.data(), std::max<size_t>(1, sk16.size()) * sizeof(unsigned short));
+  const size_t o_sk = blob.add(sk16.data(), std::max<size_t>(1, sk16.size()) * sizeof(unsigned));
   // home lists for the interpolation to the sensors: each sensor once, in
   // the tile holding its footprint origin, sensors ascending per tile
   std::vector<int> hcnt(ntiles + 1, 0), home(M);
@@ -460,7 +460,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.slot_off = static_cast<const int*>(at(o_soff));
   dp.slot_sens = static_cast<const int*>(at(o_ssens));
   dp.slot_w = at(o_sw);
-  dp.slot_k = static_cast<const unsigned short*>(at(o_sk));
+  dp.slot_k = static_cast<const unsigned*>(at(o_sk));
   dp.home_off = static_cast<const int*>(at(o_hoff));
   dp.home_sens = static_cast<const int*>(at(o_hsens));
   dp.dcx = at(o_dcx);

@@ -54,7 +54,7 @@ struct DevPlan {
   const int* slot_off = nullptr;  // [tiles_x*patches_y+1] packed slots of each 16 x kPatchRows patch (CSR)
   const int* slot_sens = nullptr; // [slots][kSlotK] sensor ids of each slot, -1 for an empty place
   const void* slot_w = nullptr;   // [slots][64] each lane's weight wx*wy (0 where no sensor covers it)
-  const unsigned short* slot_k = nullptr; // [slots][64] places in their slots of the lane's sensors for the
+  const unsigned* slot_k = nullptr;       // [slots][64] places in their slots of the lane's sensors for the
                                           // kSlotBatch slots from this one on (2 bits each, 0 past the patch)
   int patches_y = 0;
   const int* home_off = nullptr;  // [tiles+1] sensors whose footprint starts in each tile (CSR)
@@ -73,7 +73,7 @@ constexpr int kSpreadTile = 16;  // spread tile edge (grid points)
 constexpr int kPatchRows = 4;    // rows of the spread's one-wave patch (16 x 4 grid points)
 constexpr int kSlotK = 4;        // sensors per packed spread slot
 constexpr int kSpreadGroups = 2; // spread bin groups (16 bins each) per work-group
-constexpr int kSlotBatch = 8;    // spread slots staged per round (their places fit one 16-bit word)
+constexpr int kSlotBatch = 8;    // spread slots staged per round (their places fit one 32-bit word)
 // bytes kept free behind the per-sensor band values: the spread's 16-byte
 // loads to LDS may read 8 bytes past the last sensor's row
 constexpr size_t kBandTail = 16;
@@ -167,7 +167,7 @@ struct TemporalBA {
   const void* hw; const void* deap; FftView fd; int M, Nt, n0, b_lo, nb; void* Gt;
 };
 struct SpreadBA {
-  const void* Gt; const int* slot_off; const int* slot_sens; const void* slot_w; const unsigned short* slot_k;
+  const void* Gt; const int* slot_off; const int* slot_sens; const void* slot_w; const unsigned* slot_k;
   int nb, n_x, n_y, tiles_x, nchunks; void* U;
 };
 struct FftXBA {

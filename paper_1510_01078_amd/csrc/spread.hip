@@ -62,7 +62,7 @@ template <typename T, bool KAHAN>
 __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, int nb,
                                                  const int* __restrict__ slot_off,
                                                  const int* __restrict__ slot_sens, const T* __restrict__ slot_w,
-                                                 const unsigned short* __restrict__ slot_k, int n_x, int n_y,
+                                                 const unsigned* __restrict__ slot_k, int n_x, int n_y,
                                                  int tiles_x, int nchunks, int b_begin, int b_end,
                                                  cx<T>* __restrict__ U, int bx) {
   constexpr int BC = kSpreadBins, K = kSlotK, SB = kSlotBatch;
@@ -72,7 +72,7 @@ __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, i
   constexpr int EL = 16 / int(sizeof(cx<T>));  // bins per 16-byte load
   constexpr int NLD = EPL / EL;                  // loads per lane per round
   constexpr int LSTRIDE = 64 * EL;               // elements between two loads' blocks
-  static_assert(ROWS * LPR == 64 && BC % LPR == 0 && EPL % EL == 0 && SB * 2 <= 16 && K <= 4, "staging layout");
+  static_assert(ROWS * LPR == 64 && BC % LPR == 0 && EPL % EL == 0 && SB * 2 <= 32 && K <= 4, "staging layout");
   __shared__ __align__(16) cx<T> s_g[NLD * LSTRIDE];
   const int ngroups = (nchunks + kSpreadGroups - 1) / kSpreadGroups;
   const int grp = bx % ngroups;  // bin groups vary fastest: neighbours share the patch's slots
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(64) void k_spread_slots(const cx<T>* __restrict__ G
                                                      const int* __restrict__ slot_off,
                                                      const int* __restrict__ slot_sens,
                                                      const T* __restrict__ slot_w,
-                                                     const unsigned short* __restrict__ slot_k, int n_x, int n_y,
+                                                     const unsigned* __restrict__ slot_k, int n_x, int n_y,
                                                      int tiles_x, int nchunks, int b_begin, int b_end,
                                                      cx<T>* __restrict__ U) {
   spread_slot_body<T, KAHAN>(Gt, nb, slot_off, slot_sens, slot_w, slot_k, n_x, n_y, tiles_x, nchunks, b_begin,
