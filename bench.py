@@ -67,8 +67,8 @@ def stage_bytes(plan, p, eb):
         spread_bytes(plan, p, eb),                            # spread
         nb * nyo * nxo * c + nb * Nx * nyo * c,               # FFT along x with crop
         nb * Nx * nyo * c + Nx * Ny * nb * c,                 # FFT along y, crop, deconvolve
-        Nx * Ny * nb * c + Nx * Ny * lh * c,                  # gather + weight
-        3 * 2 * Nx * Ny * lh * c // 2 + Nx * Ny * lh * c + Nx * Ny * Nz * eb,  # inverse passes
+        Nx * Ny * nb * c + Nx * Ny * lh * c,                  # gather + weight + inverse x pass (one write)
+        3 * Nx * Ny * lh * c + Nx * Ny * Nz * eb,             # inverse y pass (read + write), z pass (read, write f)
     ]
 
 

@@ -274,8 +274,10 @@ pat_status pat_batch_destroy(pat_batch* batch);
  * stage to ms[0..nstage-1] (nstage <= PAT_TIMING_STAGES), the number of
  * recorded calls to *calls, and destroys the events. Stages: 0 temporal FFT,
  * 1 lateral spread, 2 lateral FFT along x, 3 lateral FFT along y with
- * deconvolution, 4 temporal interpolation and weight, 5 inverse FFT (the
- * spread and x-FFT run in rounds over bins; their rounds are summed). Calls
+ * deconvolution, 4 temporal interpolation and weight fused with the inverse
+ * FFT along x (pat_spectrum: the interpolation alone), 5 the inverse FFT's
+ * y and z passes (the spread and x-FFT run in rounds over bins; their rounds
+ * are summed). Calls
  * of pat_forward and pat_forward_dxy add each kernel's time to the stage it
  * transposes (5: forward 3-D FFT, 4: transposed interpolation, 3 and 2:
  * transposed lateral FFTs, 1: interpolation to the sensors, 0: transposed

@@ -559,10 +559,11 @@ pat_status run_traces_in(pat_plan* P, const void* g, void* out, void* ws, hipStr
     mark(4);
     return PAT_OK;
   }
+  // the gather and the inverse transform along x run as one kernel
   const int mode = op == OP_ADJOINT ? patk::GATHER_ADJOINT : patk::GATHER_IMAGE;
-  if ((e = patk::launch_gather<T>(dp, A, B, mode, s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_gather_x<T>(dp, A, B, mode, s)) != hipSuccess) return to_status(e);
   mark(4);
-  if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s)) != hipSuccess) return to_status(e);
+  if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s, true)) != hipSuccess) return to_status(e);
   mark(5);
   return PAT_OK;
 }

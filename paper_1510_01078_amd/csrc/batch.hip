@@ -19,7 +19,7 @@
 using namespace patint;
 
 namespace {
-constexpr int kStages = 8;  // temporal, spread, fft x, fft y, gather, inverse x, inverse y, c2r z
+constexpr int kStages = 7;  // temporal, spread, fft x, fft y, gather + inverse x, inverse y, c2r z
 // default persistent grid: 64 work-groups per CU of a 256-CU MI355X, each
 // looping over the work items after loading the group's arguments once
 // (measured best among 0, 4096, 16384 and 65536 on the 32-problem batch)
@@ -97,8 +97,8 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
   std::vector<patk::FftXBA> a2(P);
   std::vector<patk::FftYBA> a3(P);
   std::vector<patk::GatherBA> a4(P);
-  std::vector<patk::CfftBA> a5(P), a6(P);
-  std::vector<patk::C2rBA> a7(P);
+  std::vector<patk::CfftBA> a5(P);
+  std::vector<patk::C2rBA> a6(P);
   std::vector<int> pre[kStages];
   for (auto& v : pre) v.assign(P + 1, 0);
   size_t lds[kStages] = {};
@@ -136,27 +136,27 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A};
     pre[3][p + 1] = gx3 * d.Nx;
     lds[3] = std::max(lds[3], size_t(bins) * patk::lseq(d.n_y) * c);
-    // stage 4: temporal interpolation and weight (image-ready spectrum)
-    a4[p] = patk::GatherBA{A, d.hcoef, d.nb, d.b_lo, d.Nx, d.Ny, d.Nz, d.w_t, d.hdeg,
-                           d.s_per_k, d.kxu, d.kyu, d.kzu, d.two_c, d.n0_over_nt, d.inv_vol, Bw};
-    pre[4][p + 1] = int((size_t(d.Nx) * d.Ny * Lh + 255) / 256);
-    // stages 5, 6: inverse transforms along x and y (in place on the spectrum)
+    // stage 4: temporal interpolation and weight (image-ready spectrum) fused
+    // with the inverse transform along x
     const int lcx = patk::fft_batch<T>(d.Nx, icfg.threads, icfg.cap);
     const int gx5 = (Lh + lcx - 1) / lcx;
-    a5[p] = patk::CfftBA{Bw, patk::as_view(d.f_Nx), d.Ny, Lh, lcx, gx5};
-    pre[5][p + 1] = gx5 * d.Ny;
-    lds[5] = std::max(lds[5], size_t(lcx) * patk::lseq(d.Nx) * c);
+    a4[p] = patk::GatherBA{A, d.hcoef, d.nb, d.b_lo, d.Nx, d.Ny, d.Nz, d.w_t, d.hdeg,
+                           d.s_per_k, d.kxu, d.kyu, d.kzu, d.two_c, d.n0_over_nt, d.inv_vol, Bw,
+                           patk::as_view(d.f_Nx), lcx, gx5};
+    pre[4][p + 1] = gx5 * d.Ny;
+    lds[4] = std::max(lds[4], size_t(lcx) * patk::lseq(d.Nx) * c);
+    // stage 5: inverse transform along y (in place on the spectrum)
     const int lcy = patk::fft_batch<T>(d.Ny, icfg.threads, icfg.cap);
     const int gx6 = (Lh + lcy - 1) / lcy;
-    a6[p] = patk::CfftBA{Bw, patk::as_view(d.f_Ny), d.Ny, Lh, lcy, gx6};
-    pre[6][p + 1] = gx6 * d.Nx;
-    lds[6] = std::max(lds[6], size_t(lcy) * patk::lseq(d.Ny) * c);
-    // stage 7: complex-to-real along z into the caller's image
+    a5[p] = patk::CfftBA{Bw, patk::as_view(d.f_Ny), d.Ny, Lh, lcy, gx6};
+    pre[5][p + 1] = gx6 * d.Nx;
+    lds[5] = std::max(lds[5], size_t(lcy) * patk::lseq(d.Ny) * c);
+    // stage 6: complex-to-real along z into the caller's image
     const int rz = patk::fft_batch<T>(d.Nz, icfg.threads, icfg.cap);
     const long long nrows = (long long)d.Nx * d.Ny;
-    a7[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
-    pre[7][p + 1] = int((nrows + rz - 1) / rz);
-    lds[7] = std::max(lds[7], size_t(rz) * patk::lseq(d.Nz) * c);
+    a6[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
+    pre[6][p + 1] = int((nrows + rz - 1) / rz);
+    lds[6] = std::max(lds[6], size_t(rz) * patk::lseq(d.Nz) * c);
   }
   for (auto& v : pre) {
     for (int p = 0; p < P; ++p) {
@@ -174,7 +174,6 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
   oa[4] = blob.add(a4.data(), a4.size() * sizeof(a4[0]));
   oa[5] = blob.add(a5.data(), a5.size() * sizeof(a5[0]));
   oa[6] = blob.add(a6.data(), a6.size() * sizeof(a6[0]));
-  oa[7] = blob.add(a7.data(), a7.size() * sizeof(a7[0]));
   for (int i = 0; i < kStages; ++i) op[i] = blob.add(pre[i].data(), pre[i].size() * sizeof(int));
   G.table_bytes = align_up(blob.bytes.size());
   G.tables = dev_alloc(B->alloc_desc, G.table_bytes);
@@ -260,9 +259,8 @@ pat_status run_batch(pat_batch* B, const void* const* g, void* const* f, hipStre
     if ((e = patk::launch_fft_x_batch<T>(G.st[2], io, s)) != hipSuccess) return to_status(e);
     if ((e = patk::launch_fft_y_batch<T>(G.st[3], io, s)) != hipSuccess) return to_status(e);
     if ((e = patk::launch_gather_batch<T>(G.st[4], io, s)) != hipSuccess) return to_status(e);
-    if ((e = patk::launch_cfft_x_inv_batch<T>(G.st[5], io, s)) != hipSuccess) return to_status(e);
-    if ((e = patk::launch_cfft_y_inv_batch<T>(G.st[6], io, s)) != hipSuccess) return to_status(e);
-    if ((e = patk::launch_c2r_z_batch<T>(G.st[7], io, s)) != hipSuccess) return to_status(e);
+    if ((e = patk::launch_cfft_y_inv_batch<T>(G.st[5], io, s)) != hipSuccess) return to_status(e);
+    if ((e = patk::launch_c2r_z_batch<T>(G.st[6], io, s)) != hipSuccess) return to_status(e);
   }
   return PAT_OK;
 }

@@ -88,25 +88,16 @@ enum { MODE_IMAGE = 0, MODE_PHYSICAL = 1, MODE_ADJOINT = 2 };
 // WT > 0: compile-time tap count with the coefficients staged in LDS at
 // `coefs` (stage_tap_coefs, before the call); WT = 0: runtime wt, coefficients
 // read from hcoef.
+// One spectrum value F(jj, kk, l) of the given mode.
 template <typename T, int MODE, int WT = 0>
-__device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
-                                            double s_per_k, double kxu, double kyu, double kzu, double two_c,
-                                            double n0_over_nt, double scale, int wt, int deg,
-                                            const T* __restrict__ hcoef, cx<T>* __restrict__ Fh, int bx,
-                                            const T* coefs = nullptr) {
-  const int Lh = Nz / 2 + 1;
-  const long long total = (long long)Nx * Ny * Lh;
-  const long long idx = (long long)bx * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  const int l = int(idx % Lh);
-  const long long col = idx / Lh;
-  const int kk = int(col % Ny);
-  const int jj = int(col / Ny);
+__device__ __forceinline__ cx<T> gather_point(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                              double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                              double n0_over_nt, double scale, int wt, int deg,
+                                              const T* __restrict__ hcoef, int jj, int kk, int l,
+                                              const T* coefs) {
   const bool zero_l = MODE == MODE_ADJOINT ? (l == Nz / 2) : (l == 0 || l == Nz / 2);
-  if (zero_l || jj == Nx / 2 || kk == Ny / 2) {
-    Fh[idx] = cx<T>{T(0), T(0)};
-    return;
-  }
+  if (zero_l || jj == Nx / 2 || kk == Ny / 2) return cx<T>{T(0), T(0)};
+  const long long col = (long long)jj * Ny + kk;
   const int j = jj < Nx / 2 ? jj : jj - Nx;
   const int k = kk < Ny / 2 ? kk : kk - Ny;
   const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
@@ -150,13 +141,30 @@ __device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb
   if (MODE == MODE_ADJOINT) {
     const cx<T> ph{T(tp.cs * scale), T(tp.sn * scale)};
     const cx<T> a = cmul(acc, ph), b = cmul(acc2, ph);
-    Fh[idx] = cx<T>{a.x + b.x, a.y - b.y};
-    return;
+    return cx<T>{a.x + b.x, a.y - b.y};
   }
   double wgt = two_c * Kz / Kabs * scale;
   if (MODE == MODE_PHYSICAL && ((jj + kk) & 1)) wgt = -wgt;
   const cx<T> ph{T(wgt * tp.cs), T(wgt * tp.sn)};
-  Fh[idx] = cmul(acc, ph);
+  return cmul(acc, ph);
+}
+
+template <typename T, int MODE, int WT = 0>
+__device__ __forceinline__ void gather_body(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                            double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                            double n0_over_nt, double scale, int wt, int deg,
+                                            const T* __restrict__ hcoef, cx<T>* __restrict__ Fh, int bx,
+                                            const T* coefs = nullptr) {
+  const int Lh = Nz / 2 + 1;
+  const long long total = (long long)Nx * Ny * Lh;
+  const long long idx = (long long)bx * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int l = int(idx % Lh);
+  const long long col = idx / Lh;
+  const int kk = int(col % Ny);
+  const int jj = int(col / Ny);
+  Fh[idx] = gather_point<T, MODE, WT>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt,
+                                      deg, hcoef, jj, kk, l, coefs);
 }
 
 template <typename T, int MODE, int WT>
@@ -169,6 +177,69 @@ __global__ __launch_bounds__(256) void k_gather(const cx<T>* __restrict__ Gh, in
   __syncthreads();
   gather_body<T, MODE, WT>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt, deg, hcoef,
                            Fh, blockIdx.x, coefs);
+}
+
+// Gather fused with the first pass of the inverse 3-D FFT (image and
+// adjoint modes): a work-group owns one y mode kk and a run of lchunk z
+// modes, computes the spectrum for every x mode into LDS, transforms along x
+// there (the same transform and layout as the inverse x pass) and writes the
+// x-transformed values once. The spectrum itself never goes through HBM.
+template <typename T, int MODE, int WT, int NCT>
+__device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx, int Ny, int Nz,
+                                              double s_per_k, double kxu, double kyu, double kzu, double two_c,
+                                              double n0_over_nt, double scale, int wt, int deg,
+                                              const T* __restrict__ hcoef, int lchunk, FftDesc<T> fd, int wm,
+                                              cx<T>* __restrict__ F, int bx, int kk, const T* coefs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int Lh = Nz / 2 + 1;
+  const int bstride = lseq(Nx);
+  const int l0 = bx * lchunk;
+  const int nl = min(lchunk, Lh - l0);
+  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
+  if constexpr (NCT > 0)
+    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  __syncthreads();
+  const FastDiv div_nl(nl);
+  for (int q = tid; q < nl * Nx; q += nthr) {
+    const int jj = div_nl(q);
+    const int li = q - jj * nl;
+    buf[li * bstride + lpos(jj)] =
+        gather_point<T, MODE, WT>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt,
+                                  deg, hcoef, jj, kk, l0 + li, coefs);
+  }
+  __syncthreads();
+  if constexpr (NCT > 0)
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nl, twl, tid);
+  else
+    fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+  __syncthreads();
+  staged_copy<kFftMaxV>(
+      nl * Nx, tid, nthr,
+      [&](int q) {
+        const int jj = div_nl(q);
+        return buf[(q - jj * nl) * bstride + lpos(jj)];
+      },
+      [&](int q, cx<T> v) {
+        const int jj = div_nl(q);
+        F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)] = v;
+      });
+}
+
+template <typename T, int MODE, int WT, int NCT>
+__global__ __launch_bounds__(kFftThreads) void k_gather_x(const cx<T>* __restrict__ Gh, int nb, int b_lo, int Nx,
+                                                        int Ny, int Nz, double s_per_k, double kxu, double kyu,
+                                                        double kzu, double two_c, double n0_over_nt, double scale,
+                                                        int wt, int deg, const T* __restrict__ hcoef, int lchunk,
+                                                        FftDesc<T> fd, int wm, cx<T>* __restrict__ F) {
+  __shared__ T coefs[kMaxTapCoefs];
+  stage_tap_coefs<T, WT>(coefs, hcoef, deg);  // visible after the body's first barrier
+  // neighbouring groups share the 128-byte lines of the z runs: keep them on one XCD
+  const int gl = xcd_linear();
+  const int kk = gl / int(gridDim.x);
+  gather_x_body<T, MODE, WT, NCT>(Gh, nb, b_lo, Nx, Ny, Nz, s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale, wt, deg,
+                                  hcoef, lchunk, fd, wm, F, gl - kk * int(gridDim.x), kk, coefs);
 }
 
 // Compile-time tap counts: every even w_t in 2..16 (the plan's range).
@@ -185,6 +256,41 @@ static hipError_t wt_pick(int wt, F&& f) {
     case 16: return f(std::integral_constant<int, 16>{});
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T>
+hipError_t launch_gather_x(const DevPlan& p, const void* Gh, void* F, int mode, hipStream_t s) {
+  if (mode != GATHER_IMAGE && mode != GATHER_ADJOINT) return hipErrorInvalidValue;
+  if (p.w_t * (p.hdeg + 1) > kMaxTapCoefs) return hipErrorInvalidValue;
+  const int Lh = p.Nz / 2 + 1;
+  const FftCfg cfg = inv_cfg();
+  const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
+  const size_t lds = (size_t(lc) * lseq(p.Nx) + p.Nx) * sizeof(cx<T>);
+  const dim3 grid((Lh + lc - 1) / lc, p.Ny);
+  const cx<T>* in = static_cast<const cx<T>*>(Gh);
+  cx<T>* out = static_cast<cx<T>*>(F);
+  const T* hc = static_cast<const T*>(p.hcoef);
+  const bool adj = mode == GATHER_ADJOINT;
+  const double scale = adj ? p.adj_scale : p.inv_vol;
+  return wt_pick(p.w_t, [&](auto w) {
+    constexpr int WT = decltype(w)::value;
+    return ct_pick(CtInverse{}, p.Nx, [&](auto c) {
+      constexpr int NCT = decltype(c)::value;
+      const void* kern = adj ? reinterpret_cast<const void*>(&k_gather_x<T, MODE_ADJOINT, WT, NCT>)
+                             : reinterpret_cast<const void*>(&k_gather_x<T, MODE_IMAGE, WT, NCT>);
+      hipError_t e = allow_lds(kern, lds);
+      if (e != hipSuccess) return e;
+      if (adj)
+        hipLaunchKernelGGL((k_gather_x<T, MODE_ADJOINT, WT, NCT>), grid, dim3(cfg.threads), lds, s, in, p.nb, p.b_lo,
+                           p.Nx, p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, scale, p.w_t,
+                           p.hdeg, hc, lc, as_desc<T>(p.f_Nx), cfg.wave, out);
+      else
+        hipLaunchKernelGGL((k_gather_x<T, MODE_IMAGE, WT, NCT>), grid, dim3(cfg.threads), lds, s, in, p.nb, p.b_lo,
+                           p.Nx, p.Ny, p.Nz, p.s_per_k, p.kxu, p.kyu, p.kzu, p.two_c, p.n0_over_nt, scale, p.w_t,
+                           p.hdeg, hc, lc, as_desc<T>(p.f_Nx), cfg.wave, out);
+      return hipGetLastError();
+    });
+  });
 }
 
 template <typename T>
@@ -388,12 +494,16 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
   });
 }
 
-// Batched form of the reconstruction's interpolation (image-ready spectrum).
-// WT > 0: every problem of the group has WT taps; a work-group restages the
-// tap coefficients in LDS when its next work item belongs to another problem.
+// Batched form of the reconstruction's interpolation (image-ready spectrum)
+// fused with the inverse transform along x, each work item as in the
+// single-problem launch (same arithmetic, same bits; the runtime-planned
+// transform, as the problems' lengths differ). WT > 0: every problem of the
+// group has WT taps; a work-group restages the tap coefficients in LDS when
+// its next work item belongs to another problem.
 template <typename T, int WT>
-__global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict__ args, const int* __restrict__ prefix,
-                             int nprob, int total, BatchIO io) {
+__global__ __launch_bounds__(kFftThreads) void k_gather_batch(const GatherBA* __restrict__ args,
+                                                            const int* __restrict__ prefix, int nprob, int total,
+                                                            BatchIO io) {
   __shared__ BatchMeta<GatherBA> meta;
   __shared__ T coefs[WT > 0 ? kMaxTapCoefs : 1];
   batch_meta_load(meta, args, prefix, nprob);
@@ -402,16 +512,17 @@ __global__ __launch_bounds__(256) void k_gather_batch(const GatherBA* __restrict
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const GatherBA a = batch_args(meta, p);
     if constexpr (WT > 0) {
-      if (p != staged) {
+      if (p != staged) {  // visible after the body's first barrier
         stage_tap_coefs<T, WT>(coefs, static_cast<const T*>(a.hcoef), a.deg);
-        __syncthreads();
         staged = p;
       }
     }
-    gather_body<T, MODE_IMAGE, WT>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k, a.kxu,
-                                   a.kyu, a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg,
-                                   static_cast<const T*>(a.hcoef), static_cast<cx<T>*>(a.Fh), w - meta.prefix[p],
-                                   coefs);
+    const int local = w - meta.prefix[p];
+    const int kk = local / a.gx;
+    gather_x_body<T, MODE_IMAGE, WT, 0>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k,
+                                        a.kxu, a.kyu, a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg,
+                                        static_cast<const T*>(a.hcoef), a.lchunk, view_desc<T>(a.fd), 0,
+                                        static_cast<cx<T>*>(a.Fh), local - kk * a.gx, kk, coefs);
     __syncthreads();
   }
 }
@@ -433,6 +544,7 @@ hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStrea
 
 #define PATK_INST(T)                                                                     \
   template hipError_t launch_gather<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
+  template hipError_t launch_gather_x<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
   template size_t scatter_lds_bytes<T>(const DevPlan&);                                  \
   template hipError_t launch_scatter<T>(const DevPlan&, const void*, void*, int, hipStream_t); \
   template hipError_t launch_gather_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);

@@ -200,10 +200,10 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
 
 // In-place transforms of the half spectrum along x and y (INV: e^{+i}).
 template <typename T, bool INV>
-static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_t s) {
+static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_t s, int first_pass = 0) {
   const int Lh = p.Nz / 2 + 1;
   const FftCfg cfg = inv_cfg();
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = first_pass; pass < 2; ++pass) {
     const bool along_x = (pass == 0) == x_first;
     hipError_t e;
     if (along_x) {
@@ -237,9 +237,9 @@ static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_
 }
 
 template <typename T>
-hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s) {
+hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s, bool x_done) {
   cx<T>* F = static_cast<cx<T>*>(Fh);
-  hipError_t e = launch_xy<T, true>(p, F, true, s);
+  hipError_t e = launch_xy<T, true>(p, F, true, s, x_done ? 1 : 0);
   if (e != hipSuccess) return e;
   const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
@@ -275,22 +275,6 @@ hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t 
 
 // Batched forms of the inverse passes.
 template <typename T>
-__global__ __launch_bounds__(kFftThreads) void k_cfft_x_inv_batch(const CfftBA* __restrict__ args,
-                                                                  const int* __restrict__ prefix, int nprob, int total,
-                                                                  BatchIO io) {
-  __shared__ BatchMeta<CfftBA> meta;
-  batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
-    const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
-    const CfftBA a = batch_args(meta, p);
-    const int local = w - meta.prefix[p];
-    const int by = local / a.gx;
-    cfft_x_body<T, true>(static_cast<cx<T>*>(a.F), a.Ny, a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
-    __syncthreads();
-  }
-}
-
-template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* __restrict__ args,
                                                                   const int* __restrict__ prefix, int nprob, int total,
                                                                   BatchIO io) {
@@ -322,16 +306,6 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __rest
 }
 
 template <typename T>
-hipError_t launch_cfft_x_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
-  if (st.total <= 0) return hipSuccess;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_x_inv_batch<T>), st.lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cfft_x_inv_batch<T>), dim3(batch_grid(st)), dim3(kFftThreads), st.lds, s,
-                     static_cast<const CfftBA*>(st.args), st.prefix, st.nprob, st.total, io);
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_cfft_y_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
   if (st.total <= 0) return hipSuccess;
   hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_cfft_y_inv_batch<T>), st.lds);
@@ -352,9 +326,8 @@ hipError_t launch_c2r_z_batch(const BatchStage& st, const BatchIO& io, hipStream
 }
 
 #define PATK_INST(T)                                                                \
-  template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t); \
+  template hipError_t launch_inverse<T>(const DevPlan&, void*, T*, hipStream_t, bool); \
   template hipError_t launch_forward3d<T>(const DevPlan&, const T*, void*, hipStream_t); \
-  template hipError_t launch_cfft_x_inv_batch<T>(const BatchStage&, const BatchIO&, hipStream_t); \
   template hipError_t launch_cfft_y_inv_batch<T>(const BatchStage&, const BatchIO&, hipStream_t); \
   template hipError_t launch_c2r_z_batch<T>(const BatchStage&, const BatchIO&, hipStream_t);
 PATK_INST(float)

@@ -104,7 +104,12 @@ enum { GATHER_IMAGE = 0, GATHER_PHYSICAL = 1, GATHER_ADJOINT = 2 };
 template <typename T>
 hipError_t launch_gather(const DevPlan& p, const void* Gh, void* Fh, int mode, hipStream_t s);
 template <typename T>
-hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s);
+hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s, bool x_done = false);
+// Gather (GATHER_IMAGE or GATHER_ADJOINT) fused with the inverse transform
+// along x: leaves what launch_gather + the x pass of launch_inverse would;
+// finish with launch_inverse(..., x_done = true).
+template <typename T>
+hipError_t launch_gather_x(const DevPlan& p, const void* Gh, void* F, int mode, hipStream_t s);
 
 // Forward model. f -> Dh (real-to-complex along z, forward FFTs along y, x)
 template <typename T>
@@ -176,9 +181,10 @@ struct FftXBA {
 struct FftYBA {
   const void* V; const void* dcx; const void* dcy; FftView fd; int nb, Nx, Ny, bins, gx; void* Gh;
 };
-struct GatherBA {
+struct GatherBA {  // the gather fused with the inverse transform along x
   const void* Gh; const void* hcoef; int nb, b_lo, Nx, Ny, Nz, wt, deg;
   double s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale; void* Fh;
+  FftView fd; int lchunk, gx;  // x transform (length Nx), z modes per group, groups along z
 };
 struct CfftBA {
   void* F; FftView fd; int Ny, Lh, lchunk, gx;  // Ny is used by the x pass only
@@ -210,7 +216,6 @@ template <typename T> hipError_t launch_spread_batch(const BatchStage& st, const
 template <typename T> hipError_t launch_fft_x_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 template <typename T> hipError_t launch_fft_y_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 template <typename T> hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
-template <typename T> hipError_t launch_cfft_x_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 template <typename T> hipError_t launch_cfft_y_inv_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 template <typename T> hipError_t launch_c2r_z_batch(const BatchStage& st, const BatchIO& io, hipStream_t s);
 
