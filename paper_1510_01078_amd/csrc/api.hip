@@ -181,7 +181,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
     (void)hipGetLastError();
     return PAT_ERR_HIP;
   }
-  auto seq_bytes = [&](int n) { return size_t(n + (n >> 3) + 1) * cxb; };
+  auto seq_bytes = [&](int n) { return size_t(patk::lseq(n)) * cxb; };
   if (seq_bytes(dp.n_t) > (size_t)lds_limit || seq_bytes(dp.n_x) > (size_t)lds_limit ||
       seq_bytes(dp.n_y) > (size_t)lds_limit || seq_bytes(d.nx) > (size_t)lds_limit ||
       seq_bytes(d.ny) > (size_t)lds_limit || seq_bytes(d.nz) > (size_t)lds_limit)

@@ -85,11 +85,17 @@ __device__ __forceinline__ void staged_copy(int count, int tid, int nthr, Load l
   }
 }
 
-// LDS slot of element a of a sequence: one pad slot after every 8 elements,
-// so the stride-R stores of the first radix-8 passes hit distinct banks.
-__host__ __device__ __forceinline__ constexpr int lpos(int a) { return a + (a >> 3); }
+// LDS slot of element a of a sequence: one pad slot after every
+// 2^kLdsPadShift elements, so the stride-R stores of the first radix-8
+// passes hit distinct banks. Runs of 16 measured fastest on MI355X: a pad
+// every 8 elements puts a wave's contiguous 8-byte accesses across a pad
+// (bank conflicts on every contiguous pass), runs of 32 slowed the lateral
+// x and y transforms.
+constexpr int kLdsPadShift = 4;
+constexpr int kLdsPadRun = 1 << kLdsPadShift;
+__host__ __device__ __forceinline__ constexpr int lpos(int a) { return a + (a >> kLdsPadShift); }
 // Slots one sequence of length n occupies (odd, so sequences start on different banks).
-__host__ __device__ __forceinline__ constexpr int lseq(int n) { return n + (n >> 3) + 1; }
+__host__ __device__ __forceinline__ constexpr int lseq(int n) { return n + (n >> kLdsPadShift) + 1; }
 
 // Length-R DFT in place; INV selects exp(+2 pi i rk/R).
 template <typename T, int R, bool INV>
@@ -312,10 +318,10 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
       const int f = idx / NBF;
       const int i = idx - f * NBF;
       const cx<T>* src = buf + f * BS;
-      if constexpr (NBF % 8 == 0) {
+      if constexpr (NBF % kLdsPadRun == 0) {
         const cx<T>* s0 = src + lpos(i);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[it][r] = s0[r * (NBF + NBF / 8)];
+        for (int r = 0; r < R; ++r) v[it][r] = s0[r * lpos(NBF)];
       } else {
 #pragma unroll
         for (int r = 0; r < R; ++r) v[it][r] = src[lpos(i + r * NBF)];
@@ -344,9 +350,9 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
       const int i = idx - f * NBF;
       cx<T>* dst = buf + f * BS;
       if constexpr (P == 1) {
-        // j0 = i*R; for R = 8 the outputs r land at 9i + r, else lpos per output
-        if constexpr (R == 8) {
-          cx<T>* d0 = dst + 9 * i;
+        // j0 = i*R; for R = 8 the outputs r share one padded run: lpos(8i) + r
+        if constexpr (R == 8 && kLdsPadRun % 8 == 0) {
+          cx<T>* d0 = dst + lpos(8 * i);
 #pragma unroll
           for (int r = 0; r < R; ++r) d0[r] = v[it][r];
         } else {
@@ -356,10 +362,10 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
       } else {
         const int k = i % P;
         const int j0 = (i - k) * R + k;
-        if constexpr (P % 8 == 0) {
+        if constexpr (P % kLdsPadRun == 0) {
           cx<T>* d0 = dst + lpos(j0);
 #pragma unroll
-          for (int r = 0; r < R; ++r) d0[r * (P + P / 8)] = v[it][r];
+          for (int r = 0; r < R; ++r) d0[r * lpos(P)] = v[it][r];
         } else {
 #pragma unroll
           for (int r = 0; r < R; ++r) dst[lpos(j0 + r * P)] = v[it][r];
