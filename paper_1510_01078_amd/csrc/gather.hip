@@ -30,7 +30,7 @@ __device__ __forceinline__ TapPoint tap_point(double Kabs, double s_per_k, doubl
   tp.base = base < 0 ? 0 : (base > nb - wt ? nb - wt : base);
   double q = s * n0_over_nt;
   q -= floor(q);
-  sincos(-2.0 * M_PI * q, &tp.sn, &tp.cs);
+  sincospi(-2.0 * q, &tp.sn, &tp.cs);  // e^{-2 pi i q}; no range reduction needed
   return tp;
 }
 
