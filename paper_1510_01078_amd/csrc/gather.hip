@@ -101,7 +101,11 @@ __device__ __forceinline__ cx<T> gather_point(const cx<T>* __restrict__ Gh, int 
   const int j = jj < Nx / 2 ? jj : jj - Nx;
   const int k = kk < Ny / 2 ? kk : kk - Ny;
   const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
-  const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+  // |K| and 1/|K| from one reciprocal square root (no FP64 division for W);
+  // K = 0 (the adjoint's l = 0 plane) keeps |K| = 0
+  const double K2 = Kx * Kx + Ky * Ky + Kz * Kz;
+  const double rK = K2 > 0.0 ? rsqrt(K2) : 0.0;
+  const double Kabs = K2 * rK;
   const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
   const T y = T(tp.y);
   const cx<T>* src = Gh + col * nb + tp.base;
@@ -143,7 +147,7 @@ __device__ __forceinline__ cx<T> gather_point(const cx<T>* __restrict__ Gh, int 
     const cx<T> a = cmul(acc, ph), b = cmul(acc2, ph);
     return cx<T>{a.x + b.x, a.y - b.y};
   }
-  double wgt = two_c * Kz / Kabs * scale;
+  double wgt = two_c * Kz * rK * scale;
   if (MODE == MODE_PHYSICAL && ((jj + kk) & 1)) wgt = -wgt;
   const cx<T> ph{T(wgt * tp.cs), T(wgt * tp.sn)};
   return cmul(acc, ph);

@@ -29,8 +29,16 @@ __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, in
   const int L = lseq(n_t);
   const int mbase = 2 * pairs * bx;  // first sensor of this group
   const int np = min(pairs, (M - mbase + 1) / 2);
-  for (int q = tid; q < np * L; q += nthr) buf[q] = cx<T>{T(0), T(0)};
-  __syncthreads();
+  // zero padding: only the slots no sample lands in, (n - n0) mod n_t for
+  // n = Nt .. n_t-1; they are disjoint from the samples' slots, so the fill
+  // and the sample stores need no barrier between them
+  const int npad = n_t - Nt;
+  for (int q = tid; q < np * npad; q += nthr) {
+    const int pr = q / npad;
+    int pos = Nt + (q - pr * npad) - n0;
+    if (pos < 0) pos += n_t;
+    buf[pr * L + lpos(pos)] = cx<T>{T(0), T(0)};
+  }
   const FastDiv div_nt(Nt);
   staged_copy<kFftMaxV>(
       np * Nt, tid, nthr,
