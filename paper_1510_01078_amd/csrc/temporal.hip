@@ -20,87 +20,74 @@ constexpr int kTemporalThreads = 512;
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, int Nt, int n0,
                                               const T* __restrict__ hw, const T* __restrict__ deap,
-                                              FftDesc<T> fd, int b_lo, int nb, int pairs,
-                                              cx<T>* __restrict__ Gt, int bx) {
+                                              FftDesc<T> fd, int b_lo, int nb, cx<T>* __restrict__ Gt, int bx) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_t = fd.n;
-  const int L = lseq(n_t);
-  const int mbase = 2 * pairs * bx;  // first sensor of this group
-  const int np = min(pairs, (M - mbase + 1) / 2);
+  const int m0 = 2 * bx;  // the pair's first sensor (one pair per group measured fastest on MI355X)
+  const bool has1 = m0 + 1 < M;
   // zero padding: only the slots no sample lands in, (n - n0) mod n_t for
   // n = Nt .. n_t-1; they are disjoint from the samples' slots, so the fill
   // and the sample stores need no barrier between them
-  const int npad = n_t - Nt;
-  for (int q = tid; q < np * npad; q += nthr) {
-    const int pr = q / npad;
-    int pos = Nt + (q - pr * npad) - n0;
+  for (int i = tid; i < n_t - Nt; i += nthr) {
+    int pos = Nt + i - n0;
     if (pos < 0) pos += n_t;
-    buf[pr * L + lpos(pos)] = cx<T>{T(0), T(0)};
+    buf[lpos(pos)] = cx<T>{T(0), T(0)};
   }
-  const FastDiv div_nt(Nt);
+  const T w0 = hw ? hw[m0] : T(1);
+  const T w1 = has1 ? (hw ? hw[m0 + 1] : T(1)) : T(0);
+  const T* g0 = g + size_t(m0) * Nt;
+  const T* g1 = g + size_t(has1 ? m0 + 1 : m0) * Nt;
   staged_copy<kFftMaxV>(
-      np * Nt, tid, nthr,
-      [&](int q) {
-        const int pr = div_nt(q);
-        const int n = q - pr * Nt;
-        const int m0 = mbase + 2 * pr;
-        const bool has1 = m0 + 1 < M;
+      Nt, tid, nthr,
+      [&](int n) {
         const T d = deap[n];
-        const T w0 = hw ? hw[m0] : T(1);
-        const T w1 = has1 ? (hw ? hw[m0 + 1] : T(1)) : T(0);
-        const T a = g[size_t(m0) * Nt + n] * w0 * d;
-        const T b = has1 ? g[size_t(m0 + 1) * Nt + n] * w1 * d : T(0);
+        const T a = g0[n] * w0 * d;
+        const T b = has1 ? g1[n] * w1 * d : T(0);
         return cx<T>{a, b};
       },
-      [&](int q, cx<T> v) {
-        const int pr = div_nt(q);
-        int pos = q - pr * Nt - n0;
+      [&](int n, cx<T> v) {
+        int pos = n - n0;
         if (pos < 0) pos += n_t;
-        buf[pr * L + lpos(pos)] = v;
+        buf[lpos(pos)] = v;
       });
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kTemporalThreads, 1, false>(buf, np, fd.tw, tid);
+    fft_ct<T, NCT, kTemporalThreads, 1, false>(buf, 1, fd.tw, tid);
   else
-    fft_lds<T, kFftMaxV, false>(buf, fd, np, L, tid, nthr);
-  const FastDiv div_nb(nb);
-  for (int q = tid; q < np * nb; q += nthr) {
-    const int pr = div_nb(q);
-    const int i = q - pr * nb;
-    const int m0 = mbase + 2 * pr;
+    fft_lds<T, kFftMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
+  for (int i = tid; i < nb; i += nthr) {
     const int b = b_lo + i;  // -n_t < b < n_t (the band fits in n_t bins)
     const int pb = b < 0 ? b + n_t : b;
     const int mb = b > 0 ? n_t - b : -b;
-    const cx<T> z = buf[pr * L + lpos(pb)];
-    const cx<T> zm = buf[pr * L + lpos(mb)];
+    const cx<T> z = buf[lpos(pb)];
+    const cx<T> zm = buf[lpos(mb)];
     // transform of the real part: (Z_b + conj Z_-b)/2; of the imaginary part: (Z_b - conj Z_-b)/(2i)
     Gt[size_t(m0) * nb + i] = cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-    if (m0 + 1 < M) Gt[size_t(m0 + 1) * nb + i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+    if (has1) Gt[size_t(m0 + 1) * nb + i] = cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
   }
 }
 
 template <typename T, int NCT>
 __global__ __launch_bounds__(kTemporalThreads) void k_temporal(const T* __restrict__ g, int M, int Nt, int n0,
                                                              const T* __restrict__ hw, const T* __restrict__ deap,
-                                                             FftDesc<T> fd, int b_lo, int nb, int pairs,
+                                                             FftDesc<T> fd, int b_lo, int nb,
                                                              cx<T>* __restrict__ Gt) {
-  temporal_body<T, NCT>(g, M, Nt, n0, hw, deap, fd, b_lo, nb, pairs, Gt, blockIdx.x);
+  temporal_body<T, NCT>(g, M, Nt, n0, hw, deap, fd, b_lo, nb, Gt, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted, hipStream_t s) {
   if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t) return hipErrorInvalidValue;
-  const int pairs = 1;  // one sensor pair per group measured fastest on MI355X
-  const int blocks = (p.M + 2 * pairs - 1) / (2 * pairs);
-  const size_t lds = size_t(pairs) * lseq(p.n_t) * sizeof(cx<T>);
+  const int blocks = (p.M + 1) / 2;  // one sensor pair per group
+  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
   return ct_pick(CtTemporal{}, p.n_t, [&](auto c) {
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_temporal<T, decltype(c)::value>), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_temporal<T, decltype(c)::value>), dim3(blocks), dim3(kTemporalThreads), lds, s, g, p.M,
                        p.Nt, p.n0, weighted ? static_cast<const T*>(p.hw) : nullptr, static_cast<const T*>(p.deap),
-                       as_desc<T>(p.f_nt), p.b_lo, p.nb, pairs, static_cast<cx<T>*>(Gt));
+                       as_desc<T>(p.f_nt), p.b_lo, p.nb, static_cast<cx<T>*>(Gt));
     return hipGetLastError();
   });
 }
@@ -184,7 +171,7 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const Tempo
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const TemporalBA a = batch_args(meta, p);
     temporal_body<T>(static_cast<const T*>(io.in[p]), a.M, a.Nt, a.n0, static_cast<const T*>(a.hw),
-                     static_cast<const T*>(a.deap), view_desc<T>(a.fd), a.b_lo, a.nb, 1, static_cast<cx<T>*>(a.Gt),
+                     static_cast<const T*>(a.deap), view_desc<T>(a.fd), a.b_lo, a.nb, static_cast<cx<T>*>(a.Gt),
                      w - meta.prefix[p]);
     __syncthreads();
   }
