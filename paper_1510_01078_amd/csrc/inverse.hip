@@ -127,29 +127,47 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
   const int bstride = lseq(Nz);
   const long long r0 = (long long)bx * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
+  // two real rows per complex transform: Z = X0 + i X1 (each Hermitian-
+  // extended) transforms to x0 + i x1. The DC and Nyquist bins keep their
+  // real parts only, as the real part of a single row's transform would.
+  const int np = (nr + 1) / 2;
   const FastDiv div_lh(Lh), div_nz(Nz);
+  struct Two {
+    cx<T> a, c;
+  };
   staged_copy<kFftMaxV>(
-      nr * Lh, tid, nthr, [&](int q) { return F[r0 * Lh + q]; },
-      [&](int q, cx<T> v) {
-        const int r = div_lh(q);
-        const int l = q - r * Lh;
-        buf[r * bstride + lpos(l)] = v;
-        if (l > 0 && l < Nz / 2) buf[r * bstride + lpos(Nz - l)] = cx<T>{v.x, -v.y};
+      np * Lh, tid, nthr,
+      [&](int q) {
+        const int s = div_lh(q);
+        const long long at = (r0 + 2 * s) * Lh + (q - s * Lh);
+        return Two{F[at], 2 * s + 1 < nr ? F[at + Lh] : cx<T>{T(0), T(0)}};
+      },
+      [&](int q, Two v) {
+        const int s = div_lh(q);
+        const int l = q - s * Lh;
+        cx<T>* row = buf + s * bstride;
+        if (l == 0 || l == Nz / 2) {
+          row[lpos(l)] = cx<T>{v.a.x, v.c.x};
+        } else {
+          row[lpos(l)] = cx<T>{v.a.x - v.c.y, v.a.y + v.c.x};
+          row[lpos(Nz - l)] = cx<T>{v.a.x + v.c.y, v.c.x - v.a.y};
+        }
       });
   cx<T>* twl = buf + rows * bstride;
   if constexpr (NCT > 0)
     for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nr, twl, tid);
+    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, np, twl, tid);
   else
-    fft_group<T, true>(buf, fd, nr, bstride, tid, nthr, wm);
+    fft_group<T, true>(buf, fd, np, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr,
       [&](int q) {
         const int r = div_nz(q);
-        return buf[r * bstride + lpos(q - r * Nz)].x;
+        const cx<T> v = buf[(r >> 1) * bstride + lpos(q - r * Nz)];
+        return (r & 1) ? v.y : v.x;
       },
       [&](int q, T v) { f[r0 * Nz + q] = v; });
 }
