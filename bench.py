@@ -43,15 +43,15 @@ def log(*a):
 def spread_bytes(plan, p, eb):
     """Algorithmic bytes of one spread launch: read the per-sensor band values,
     write the oversampled grid once, read the packed slot tables once (per
-    slot: 64 lane weights, 64 one-byte sensor places, 4 sensor ids) and the
-    patch offsets."""
+    slot: 64 lane weights and 4 sensor ids; per round of 8 slots one 32-bit
+    place word per lane, 32 bytes per slot) and the patch offsets."""
     info = plan.info
     nb, nxo, nyo = info["band_bins"], info["nx_over"], info["ny_over"]
     m = p.m
     read_bins = m * nb * 2 * eb
     write_grid = nb * nxo * nyo * 2 * eb
     patches = -(-nxo // 16) * -(-nyo // 4)
-    tables = info["spread_slots"] * (64 * (eb + 1) + 4 * 4) + 4 * (patches + 1)
+    tables = info["spread_slots"] * (64 * eb + 32 + 4 * 4) + 4 * (patches + 1)
     return read_bins + write_grid + tables
 
 
