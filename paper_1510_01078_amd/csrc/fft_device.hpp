@@ -21,6 +21,18 @@ struct cx {
   T x, y;
 };
 
+// Store that streams past the caches (the value is read once, later, by the
+// next kernel), as two non-temporal 32- or 64-bit stores.
+template <typename T>
+__device__ __forceinline__ void nt_store(cx<T>* p, cx<T> v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> nt_load(const cx<T>* p) {
+  return cx<T>{__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y)};
+}
+
 template <typename T>
 __device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
 template <typename T>

