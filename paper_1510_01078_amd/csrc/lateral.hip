@@ -230,9 +230,9 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
         const int bi = div_ny(q);
         return buf[bi * bstride + lpos(q - bi * n_y)];
       },
-      [&](int q, cx<T> v) {
+      [&](int q, cx<T> v) {  // non-temporal: streams out once (measured faster for the fused reader)
         const int bi = div_ny(q);
-        V[(size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y)] = v;
+        nt_store(V + (size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y), v);
       });
 }
 

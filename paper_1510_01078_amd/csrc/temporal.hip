@@ -141,8 +141,9 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal_t(const cx<T>* __
     if (pos < 0) pos += n_t;
     const cx<T> z = buf[lpos(pos)];
     const T d = deap[n];
-    g[size_t(m0) * Nt + n] = z.x * d;
-    if (has1) g[size_t(m0 + 1) * Nt + n] = z.y * d;
+    // the caller's traces: non-temporal stores (measured faster)
+    __builtin_nontemporal_store(z.x * d, g + size_t(m0) * Nt + n);
+    if (has1) __builtin_nontemporal_store(z.y * d, g + size_t(m0 + 1) * Nt + n);
   }
 }
 
