@@ -3,6 +3,11 @@
 Correlation coefficient (Appendix B, eq. corrcoeff), Tenenbaum sharpness with
 the Sobel operator normalised by the element count (Appendix B), maximum
 intensity projections, and the relative L2 distance used for parity.
+
+Test infrastructure: only the tests, the smoke check and the benchmark's CPU
+leg use this module. Pinned in tests/test_oracle_quality_pins.py (numpy's
+correlation routine and exact affine and orthogonal cases; closed-form Sobel
+responses of linear ramps and of an impulse; a one-hot volume).
 """
 from __future__ import annotations
 
