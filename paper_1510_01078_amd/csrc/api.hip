@@ -14,6 +14,7 @@
 #include "kernels_common.hpp"
 #include "pat_nufft.h"
 #include "plan_internal.hpp"
+#include "plan_sizes.hpp"
 #include "window.hpp"
 
 using namespace patint;
@@ -21,20 +22,7 @@ using namespace patint;
 namespace {
 
 
-inline bool smooth235(long n) {
-  if (n < 1) return false;
-  for (int p : {2, 3, 5})
-    while (n % p == 0) n /= p;
-  return n == 1;
-}
-
-// smallest even 2,3,5-smooth integer >= n
-inline int next_smooth_even(double v) {
-  long n = (long)std::ceil(v - 1e-9);
-  if (n < 2) n = 2;
-  while (!(smooth235(n) && n % 2 == 0)) ++n;
-  return (int)n;
-}
+using patsz::next_smooth_even;
 
 // exact-division multiplier for x < 2^16, d < 2^16 (0 encodes d == 1)
 inline uint32_t div_magic(int d) { return d == 1 ? 0u : uint32_t((uint64_t(1) << 32) / uint64_t(d) + 1); }
@@ -144,30 +132,24 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.n_x = next_smooth_even(std::max(d.sigma_xy * d.nx, double(d.width_xy)));
   dp.n_y = next_smooth_even(std::max(d.sigma_xy * d.ny, double(d.width_xy)));
   const bool linear_t = d.temporal_interp == PAT_INTERP_LINEAR;
-  dp.n_t = next_smooth_even(d.sigma_t * Nt);
   // band of oversampled temporal bins the interpolation reads: |K| from 0 (the
   // l = 0 plane, read by the forward model and the adjoint) to the largest
   // non-Nyquist lattice point, w_t/2 bins of margin below and w_t/2 + 1
-  // above. Short traces can need more bins than smooth(sigma_t*Nt) holds;
-  // the FFT is then lengthened until the band fits (more oversampling).
+  // above, rounded up to an even count (plan_sizes.hpp)
   {
     const int wt_taps = linear_t ? 2 : d.width_t;
     const double Kx = (d.nx / 2 - 1) * 2.0 * M_PI / d.lx, Ky = (d.ny / 2 - 1) * 2.0 * M_PI / d.ly;
     const double Kz = (d.nz / 2 - 1) * 2.0 * M_PI / d.lz;
     const double kmax = std::sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
-    for (;;) {
-      const double smax = kmax * d.c * d.dt * dp.n_t / (2.0 * M_PI);
-      const long blo = -wt_taps / 2;
-      const long bhi = (long)std::floor(smax) + wt_taps / 2 + 1;
-      if (bhi - blo + 1 <= dp.n_t && bhi < dp.n_t) {
-        dp.b_lo = (int)blo;
-        dp.nb = (int)(bhi - blo + 1);
-        break;
-      }
-      if (dp.n_t >= 8192) return PAT_ERR_UNSUPPORTED;  // |omega| dt near or past pi
-      dp.n_t = next_smooth_even(dp.n_t + 1);
-    }
+    const patsz::Band band = patsz::temporal_band(d.sigma_t, Nt, wt_taps, kmax, d.c, d.dt);
+    if (!band.ok) return PAT_ERR_UNSUPPORTED;  // |omega| dt near or past pi
+    dp.n_t = band.n_t;
+    dp.b_lo = band.b_lo;
+    dp.nb = band.nb;
   }
+  // the spread stages each sensor's band row with 16-byte loads: rows must
+  // start on 16-byte boundaries (the workspace regions are 256-byte aligned)
+  if ((size_t(dp.nb) * 2 * sizeof(T)) % 16 != 0) return PAT_ERR_UNSUPPORTED;
   // window form: samples centred on n0 = Nt/2; linear baseline: zeros appended
   // after the trace (time origin 0) and two taps
   dp.n0 = linear_t ? 0 : Nt / 2;
@@ -506,7 +488,7 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   const size_t szB = align_up(std::max(sz_V, sz_F));
   P->off_B = szA;
   P->off_C = szA + szB;
-  P->ws_bytes = szA + szB + align_up(sz_Gt + patk::kBandTail);
+  P->ws_bytes = szA + szB + align_up(sz_Gt);
   return PAT_OK;
 }
 

@@ -81,7 +81,7 @@ void problem_regions(const patk::DevPlan& d, size_t& a, size_t& b, size_t& cc) {
   const size_t lh = size_t(d.Nz / 2 + 1);
   a = align_up(std::max(size_t(d.nb) * d.n_y * d.n_x * c, size_t(d.Nx) * d.Ny * d.nb * c));
   b = align_up(std::max(size_t(d.nb) * d.Nx * d.n_y * c, size_t(d.Nx) * d.Ny * lh * c));
-  cc = align_up(size_t(d.M) * d.nb * c + patk::kBandTail);
+  cc = align_up(size_t(d.M) * d.nb * c);
 }
 
 // Stage tables of one group, with workspace pointers into `ws`.

@@ -210,6 +210,7 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
   // grid row of each strip row (periodic in y; short axes wrap more than once)
   __shared__ int s_row[R];
   for (int r = tid; r < R; r += nthr) s_row[r] = (py0 + r) % n_y;
+  __syncthreads();  // every wave reads the table in the first bin's staging loop
   for (int b = b0; b < b1; ++b) {
     for (int q = tid; q < R * gap; q += nthr) {
       const int r = div_gap(q);

@@ -74,9 +74,6 @@ constexpr int kPatchRows = 4;    // rows of the spread's one-wave patch (16 x 4 
 constexpr int kSlotK = 4;        // sensors per packed spread slot
 constexpr int kSpreadGroups = 2; // spread bin groups (16 bins each) per work-group
 constexpr int kSlotBatch = 8;    // spread slots staged per round (their places fit one 32-bit word)
-// bytes kept free behind the per-sensor band values: the spread's 16-byte
-// loads to LDS may read 8 bytes past the last sensor's row
-constexpr size_t kBandTail = 16;
 
 // Stage launchers; T = float or double. Buffers are device pointers.
 //

@@ -46,10 +46,11 @@ __device__ __forceinline__ void accum(cx<T>& a, cx<T>& c, T wt, cx<T> g) {
 // loop is the LDS row reads and the FMAs. The bin values of a round's slots
 // go from global memory straight into LDS (16-byte loads to LDS, no staging
 // registers), laid out load-major: load i of lane L lands at i*1024 + 16*L,
-// which puts the up to four rows of one slot in different banks. A load
-// starting past the band's last bin is moved onto that bin (its bins are
-// never stored); one starting on it may read 8 bytes past the row, which the
-// band-value buffer's 16-byte tail keeps in bounds for the last sensor. Each
+// which puts the up to four rows of one slot in different banks. The plan
+// keeps an even number of band bins, so every sensor's row starts on a
+// 16-byte boundary and every load starts on a whole 16-byte unit of it; a
+// load starting past the band's last unit is moved onto that unit (the bins
+// it then holds are never stored), so no load leaves its row. Each
 // grid point sums its sensors in slot order
 // (deterministic). A work-group takes kSpreadGroups consecutive bin groups of
 // its patch, so a patch with one round of slots (the usual case) reads its
@@ -115,7 +116,7 @@ __device__ __forceinline__ void spread_slot_body(const cx<T>* __restrict__ Gt, i
       __syncthreads();  // the previous round has been consumed
 #pragma unroll
       for (int i = 0; i < NLD; ++i) {
-        const int e = min(b0 + part * EPL + i * EL, nb - 1);
+        const int e = min(b0 + part * EPL + i * EL, nb - EL);  // nb is a multiple of EL
         __builtin_amdgcn_global_load_lds(static_cast<const void*>(gs + e),
                                          (__attribute__((address_space(3))) void*)(s_g + i * LSTRIDE), 16, 0, 0);
       }
