@@ -64,7 +64,9 @@ typedef enum {
   PAT_ERR_UNSUPPORTED = 2,      /* size the FFTs or kernels cannot represent */
   PAT_ERR_ALLOC = 3,            /* device allocation (or the alloc callback) failed */
   PAT_ERR_HIP = 4,              /* a HIP runtime call or kernel launch failed */
-  PAT_ERR_NOT_IMPLEMENTED = 5
+  PAT_ERR_NOT_IMPLEMENTED = 5,
+  PAT_ERR_WORKSPACE_TOO_LARGE = 6 /* pat_reconstruct_noalloc: the plan's workspace exceeds
+                                     PAT_NOALLOC_SCRATCH_BYTES */
 } pat_status;
 
 typedef enum {
@@ -266,6 +268,25 @@ pat_status pat_batch_reconstruct(pat_batch* batch, const void* const* g, void* c
 
 /* Synchronises the device, then releases the batch. NULL is ignored. */
 pat_status pat_batch_destroy(pat_batch* batch);
+
+/* f = R g, as pat_reconstruct, for callers that cannot allocate device
+ * memory when they reconstruct (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): no workspace argument, and the
+ * call allocates nothing (no hipMalloc, no allocator callback, no host
+ * allocation). The workspace is a fixed array of PAT_NOALLOC_SCRATCH_BYTES
+ * bytes inside the library, one per GPU the library runs on, reserved when
+ * the library's device code is loaded on that GPU and held until the process
+ * ends; its device address is looked up (hipGetSymbolAddress) on the first
+ * call on each device. g, f, stream and the result as pat_reconstruct (same
+ * kernels, same bits). Returns PAT_ERR_WORKSPACE_TOO_LARGE, before enqueueing
+ * anything, when nufft_plan_workspace_size exceeds PAT_NOALLOC_SCRATCH_BYTES
+ * (use pat_reconstruct with a caller workspace then). Every call on one GPU
+ * uses that GPU's one array: calls that overlap in time on the same GPU
+ * (other streams, other threads, other plans) race and give undefined
+ * results; serialise them. Nothing in the array needs clearing between
+ * calls (every stage writes what the next reads). */
+#define PAT_NOALLOC_SCRATCH_BYTES (256u * 1024u * 1024u)
+pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* g, void* f, void* stream);
 
 /* Per-stage device timing with HIP events recorded on the call's stream.
  * pat_timing_begin(plan, n) creates events for up to n subsequent compute

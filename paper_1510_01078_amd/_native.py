@@ -17,6 +17,8 @@ PAT_ERR_UNSUPPORTED = 2
 PAT_ERR_ALLOC = 3
 PAT_ERR_HIP = 4
 PAT_ERR_NOT_IMPLEMENTED = 5
+PAT_ERR_WORKSPACE_TOO_LARGE = 6
+PAT_NOALLOC_SCRATCH_BYTES = 256 * 1024 * 1024  # the library's fixed scratch for pat_reconstruct_noalloc
 
 PAT_FP64, PAT_FP32, PAT_FP32_KAHAN = 0, 1, 2
 PAT_KERNEL_GAUSSIAN, PAT_KERNEL_KAISER_BESSEL = 0, 1
@@ -86,6 +88,7 @@ SIGNATURES = {
     "pat_plan_get_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
     "nufft_plan_destroy": (C.c_int, [C.c_void_p]),
     "pat_reconstruct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "pat_reconstruct_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_spectrum": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "pat_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -784,6 +784,9 @@ const char* pat_status_str(pat_status s) {
     case PAT_ERR_ALLOC: return "PAT_ERR_ALLOC: device allocation failed";
     case PAT_ERR_HIP: return "PAT_ERR_HIP: HIP runtime error";
     case PAT_ERR_NOT_IMPLEMENTED: return "PAT_ERR_NOT_IMPLEMENTED: not implemented";
+    case PAT_ERR_WORKSPACE_TOO_LARGE:
+      return "PAT_ERR_WORKSPACE_TOO_LARGE: the plan's workspace exceeds the library's fixed scratch "
+             "(PAT_NOALLOC_SCRATCH_BYTES); use pat_reconstruct with a caller workspace";
   }
   return "unknown pat_status";
 }

@@ -4,7 +4,6 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include <map>
 #include <mutex>
 #include <type_traits>
 #include <utility>
@@ -82,20 +81,31 @@ __device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int 
 }
 
 // Allow a kernel more than the default dynamic LDS when a launch needs it.
-// The largest size granted per (kernel, device) is remembered, so repeated
-// launches (also inside a stream capture) make no runtime call.
+// The largest size granted per (kernel, device) is remembered in a fixed
+// table, so repeated launches (also inside a stream capture) make no runtime
+// call and no host allocation.
 static inline hipError_t allow_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return hipGetLastError();
+  struct Grant {
+    const void* fn;
+    int dev;
+    size_t bytes;
+  };
+  constexpr int kGrants = 256;
+  static Grant granted[kGrants];
+  static int used = 0;
   static std::mutex mu;
-  static std::map<std::pair<const void*, int>, size_t> granted;
   std::lock_guard<std::mutex> lock(mu);
-  size_t& have = granted[{fn, dev}];
-  if (bytes <= have) return hipSuccess;
+  int i = 0;
+  while (i < used && !(granted[i].fn == fn && granted[i].dev == dev)) ++i;
+  if (i < used && bytes <= granted[i].bytes) return hipSuccess;
   const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e == hipSuccess) have = bytes;
-  return e;
+  if (e != hipSuccess) return e;
+  if (i == used && used < kGrants) granted[used++] = Grant{fn, dev, 0};
+  if (i < used) granted[i].bytes = bytes;  // a full table only means the attribute is set again next time
+  return hipSuccess;
 }
 
 template <typename T>

@@ -77,12 +77,14 @@ class Plan:
     'fp32_kahan' or 'fp64') and temporal interpolation ('window': the
     NER-NUFFT; 'linear': the zero-padded FFT with linear interpolation that
     the paper compares against). The plan lives on `device` (default: the
-    current CUDA/HIP device) and uses torch's current stream there.
+    current CUDA/HIP device) and uses torch's current stream there. With
+    workspace=False the plan allocates no workspace tensor (for callers that
+    only use reconstruct_noalloc or pass their own workspace).
     """
 
     def __init__(self, sensor_xy, n_t, dt, c, shape, extent, sensor_h=None, sigma_xy=2.0, width_xy=8,
                  sigma_t=2.0, width_t=8, kernel="kaiser_bessel", precision="fp32", device=None,
-                 temporal_interp="window"):
+                 temporal_interp="window", workspace=True):
         import torch
 
         self._torch = torch
@@ -115,7 +117,8 @@ class Plan:
         info = N.PlanInfo()
         N.check(self._lib.pat_plan_get_info(handle, C.byref(info)), "pat_plan_get_info")
         self.info = {f: getattr(info, f) for f, _ in N.PlanInfo._fields_ if not f.startswith("pad")}
-        self.workspace = torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=dev)
+        self.workspace = (torch.empty(int(info.workspace_bytes), dtype=torch.uint8, device=dev)
+                          if workspace else None)
 
     # ------------------------------------------------------------------
     def _stream(self):
@@ -145,6 +148,8 @@ class Plan:
 
     def _ws(self, workspace):
         ws = self.workspace if workspace is None else workspace
+        if ws is None:
+            raise ValueError("the plan was built without a workspace: pass one")
         if ws.device != self.device or ws.numel() * ws.element_size() < self.info["workspace_bytes"]:
             raise ValueError("workspace too small or on another device")
         return ws
@@ -157,6 +162,20 @@ class Plan:
         ws = self._ws(workspace)
         N.check(self._lib.pat_reconstruct(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
                                           C.c_void_p(ws.data_ptr()), self._stream()), "pat_reconstruct")
+        return out
+
+    def reconstruct_noalloc(self, g, out):
+        """f = R g (pat_reconstruct_noalloc) into the caller's `out` with the
+        library's fixed scratch as workspace: nothing is allocated. Raises
+        PatError (PAT_ERR_WORKSPACE_TOO_LARGE) when the plan's workspace
+        exceeds the scratch. Calls overlapping in time on one GPU race."""
+        self._check_handle()
+        self._check_traces(g)
+        if out is None:
+            raise ValueError("reconstruct_noalloc writes into a caller-provided output")
+        out = self._out(out, self.shape, self.dtype)
+        N.check(self._lib.pat_reconstruct_noalloc(self._handle, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                                  self._stream()), "pat_reconstruct_noalloc")
         return out
 
     def spectrum(self, g, out=None, workspace=None):

@@ -29,7 +29,7 @@ def test_header_symbols_exported():
 
 def test_status_strings():
     lib = N.load()
-    for s in range(6):
+    for s in range(7):
         assert lib.pat_status_str(s).decode().startswith("PAT_")
     assert b"gfx950" in lib.pat_version()
 
