@@ -10,7 +10,14 @@ FP32. Prints one JSON line on stdout; progress goes to stderr.
 
 The CPU-baseline leg times the FP64 oracle on a bounded sample of the same
 workload (a few lateral x-modes, all y-modes and depths), extrapolates to the
-full grid, and compares the GPU spectrum with the oracle on that sample.
+full grid, and compares the GPU spectrum with the oracle on that sample; it
+also runs the oracle in full on the two small workloads, on all host cores
+and on one thread. Beside the headline it times: the same workload with
+compensated (Kahan) spreading, the plain FP64 form, the forward model and
+adjoint, the 32-problem batch, and the 64x64-sensor workload with Gaussian
+width-12 windows in FP32 beside FP64. Where the FP64 oracle's full headline
+image has been generated (tests/golden/make_headline_image.py), the timed
+images are compared with it.
 """
 from __future__ import annotations
 
@@ -56,9 +63,13 @@ def spread_bytes(plan, p, eb):
 
 
 def stage_bytes(plan, p, eb):
-    """Algorithmic bytes per launch of every stage (one pass over each array)."""
+    """Algorithmic bytes per launch of every stage (one pass over each array
+    it must touch). The y-FFT and the interpolation count only the (x-mode,
+    band bin) pairs inside the per-x-mode ranges the interpolation reads
+    (plan info band_pairs); the bins outside are neither transformed nor read."""
     info = plan.info
-    nb, nxo, nyo, nto = info["band_bins"], info["nx_over"], info["ny_over"], info["nt_over"]
+    nb, nxo, nyo = info["band_bins"], info["nx_over"], info["ny_over"]
+    pairs = info["band_pairs"]
     Nx, Ny, Nz = p.shape
     c = 2 * eb
     lh = Nz // 2 + 1
@@ -66,10 +77,44 @@ def stage_bytes(plan, p, eb):
         p.m * p.nt * eb + p.m * nb * c,                       # temporal: traces in, band out
         spread_bytes(plan, p, eb),                            # spread
         nb * nyo * nxo * c + nb * Nx * nyo * c,               # FFT along x with crop
-        nb * Nx * nyo * c + Nx * Ny * nb * c,                 # FFT along y, crop, deconvolve
-        Nx * Ny * nb * c + Nx * Ny * lh * c,                  # gather + weight + inverse x pass (one write)
+        pairs * nyo * c + pairs * Ny * c,                     # FFT along y, crop, deconvolve (ranges only)
+        pairs * Ny * c + Nx * Ny * lh * c,                    # gather + weight + inverse x pass (one write)
         3 * Nx * Ny * lh * c + Nx * Ny * Nz * eb,             # inverse y pass (read + write), z pass (read, write f)
     ]
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def headline_oracle_image():
+    """The FP64 oracle's image of the headline workload as written by
+    tests/golden/make_headline_image.py (float32 copy, SHA-256 checked), with
+    its metadata; (None, None) when the file has not been generated."""
+    import hashlib
+    meta_path = os.path.join(GOLDEN, "headline_oracle_image.json")
+    if not os.path.exists(meta_path):
+        return None, None
+    with open(meta_path) as fh:
+        meta = json.load(fh)
+    path = os.path.join(GOLDEN, meta["file"])
+    if not os.path.exists(path):
+        return None, None
+    h = hashlib.sha256()
+    with open(path, "rb") as fh:
+        for blk in iter(lambda: fh.read(1 << 22), b""):
+            h.update(blk)
+    if h.hexdigest() != meta["sha256"]:
+        log("headline oracle image does not match its SHA-256: not used")
+        return None, None
+    return np.load(path), meta
+
+
+def rel_l2_gpu(f, ref_np, ref_norm=None):
+    """Relative L2 distance of a device image from a host reference."""
+    import torch
+    ref = torch.from_numpy(np.ascontiguousarray(ref_np)).to(f.device, torch.float64)
+    den = float(torch.linalg.vector_norm(ref)) if ref_norm is None else ref_norm
+    return float(torch.linalg.vector_norm(f.double() - ref)) / den
 
 
 def _time_calls(fn, steps, warmup, dev):
@@ -182,26 +227,74 @@ def fp64_compare(args, p, g, dev):
             "fp32_vs_fp64_rel_l2": rel}
 
 
-def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
-    """Time the FP64 oracle on `nsample` lateral x-modes (all y-modes, all
-    depths), extrapolate to the full grid (plus the full inverse transform),
-    and compare the GPU half spectrum with the oracle on the sample."""
-    import oracle
-    from threadpoolctl import threadpool_info
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo where available)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
+
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_full(p, threads):
+    """The FP64 oracle's full reconstruction of problem p with `threads` BLAS
+    and worker threads; returns (image, seconds)."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    old = os.environ.get("ORACLE_THREADS")
+    os.environ["ORACLE_THREADS"] = str(threads)
+    try:
+        with threadpool_limits(limits=threads, user_api="blas"):
+            t0 = time.perf_counter()
+            f = oracle.reconstruct(p.xy, p.h, p.g, p.dt, p.c, p.shape, p.extent)
+            sec = time.perf_counter() - t0
+    finally:
+        if old is None:
+            os.environ.pop("ORACLE_THREADS", None)
+        else:
+            os.environ["ORACLE_THREADS"] = old
+    return f, sec
+
+
+def cpu_baseline(p, gpu_spectrum, nsample, small, seed=5):
+    """The FP64 oracle on the host cores. Main value: the headline workload
+    timed on `nsample` lateral x-modes (all y-modes, all depths),
+    extrapolated linearly in x-modes plus the full inverse transform, with the
+    GPU half spectrum compared on that sample. Beside it: full oracle runs of
+    the small workloads `small` ({name: problem}) on all cores and on one
+    thread. Returns (record, {name: oracle image on all cores})."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    cores = host_cores()
     Nx, Ny, Nz = p.shape
     X, Y, Z = p.extent
     rng = np.random.default_rng(seed)
     rows = np.sort(rng.choice(np.arange(1, Nx), size=nsample, replace=False))  # natural-order x positions
     kx, ky, kz = oracle.lattice(Nx, X), oracle.lattice(Ny, Y), oracle.lattice(Nz, Z)
-    t0 = time.perf_counter()
-    G = oracle.stage_lateral(p.xy, p.h, p.g, p.dt, Nx, Ny, X, Y, j_index=rows)
-    S = oracle.stage_temporal(G, kx[rows], ky, kz, p.c, p.dt)
-    F = oracle.apply_weight(S, kx, ky, kz, p.c, j_index=rows)
-    t_sample = time.perf_counter() - t0
-    t1 = time.perf_counter()
-    oracle.inverse(np.ones(p.shape, dtype=np.complex128), X, Y, Z)
-    t_inv = time.perf_counter() - t1
+    os.environ["ORACLE_THREADS"] = str(cores)
+    with threadpool_limits(limits=cores, user_api="blas"):
+        t0 = time.perf_counter()
+        G = oracle.stage_lateral(p.xy, p.h, p.g, p.dt, Nx, Ny, X, Y, j_index=rows)
+        S = oracle.stage_temporal(G, kx[rows], ky, kz, p.c, p.dt)
+        F = oracle.apply_weight(S, kx, ky, kz, p.c, j_index=rows)
+        t_sample = time.perf_counter() - t0
+        t1 = time.perf_counter()
+        oracle.inverse(np.ones(p.shape, dtype=np.complex128), X, Y, Z)
+        t_inv = time.perf_counter() - t1
+        blas = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
+    os.environ.pop("ORACLE_THREADS", None)
     t_full = t_sample * Nx / nsample + t_inv
     # parity on the sample: GPU layout [j mod Nx][k mod Ny][l], l = 0..Nz/2
     jj = (rows - Nx // 2) % Nx
@@ -209,13 +302,16 @@ def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
     ref = np.fft.ifftshift(F, axes=1)[:, :, (lz + Nz // 2) % Nz]
     got = gpu_spectrum[jj]
     rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    blas = [i.get("num_threads") for i in threadpool_info() if i.get("user_api") == "blas"]
-    cores = max([os.cpu_count() or 1] + [b or 1 for b in blas]) if blas else (os.cpu_count() or 1)
-    try:
-        cores = min(cores, len(os.sched_getaffinity(0)))
-    except AttributeError:
-        pass
-    return {
+    full, images = {}, {}
+    for name, q in small.items():
+        vox = float(np.prod(q.shape))
+        f_all, s_all = oracle_full(q, cores)
+        _, s_one = oracle_full(q, 1)
+        images[name] = f_all
+        full[name] = {"seconds_all_cores": round(s_all, 3), "voxels_per_s_all_cores": vox / s_all,
+                      "seconds_one_thread": round(s_one, 3), "voxels_per_s_one_thread": vox / s_one}
+        log(f"cpu baseline: full oracle {name}: {s_all:.2f} s on {cores} threads, {s_one:.2f} s on one")
+    rec = {
         "value": float(np.prod(p.shape) / t_full),
         "unit": "voxels/s",
         "cores": int(cores),
@@ -223,10 +319,37 @@ def cpu_baseline(p, gpu_spectrum, nsample, seed=5):
         "sample": f"FP64 direct-sum oracle on {nsample} of {Nx} lateral x-modes (all {Ny} y-modes, all {Nz} "
                   f"depths) in {t_sample:.1f} s, extrapolated linearly in x-modes plus the full inverse "
                   f"transform ({t_inv:.1f} s)",
+        "cpu_model": cpu_model(),
+        "blas_threads": blas,
         "seconds_sample": round(t_sample, 3),
         "seconds_extrapolated": round(t_full, 1),
         "gpu_vs_oracle_rel_l2_on_sample": rel,
+        "full_oracle_runs": full,
     }
+    return rec, images
+
+
+def bench_c2_gaussian(args, dev, ref):
+    """The 64x64-sensor workload (1024 samples -> 128^3) at oversampling 2
+    with Gaussian windows of width 12, FP32 beside the plain FP64 form: time
+    per reconstruction and relative L2 distance of each from the FP64 oracle
+    image `ref`."""
+    import torch
+    from paper_1510_01078_amd import Plan, inputs
+    q = inputs.config_problem(1)
+    settings = dict(kernel="gaussian", sigma_xy=2.0, width_xy=12, sigma_t=2.0, width_t=12)
+    out = {"workload": WORKLOADS[1], "settings": settings}
+    voxels = float(np.prod(q.shape))
+    for prec in ("fp32", "fp64"):
+        pl = Plan(q.xy, q.nt, q.dt, q.c, q.shape, q.extent, sensor_h=q.h, precision=prec, device=dev, **settings)
+        g = torch.from_numpy(np.ascontiguousarray(q.g)).to(dev, pl.dtype)
+        f = torch.empty(q.shape, dtype=pl.dtype, device=dev)
+        ms = _time_calls(lambda: pl.reconstruct(g, out=f), args.steps, args.warmup, dev)
+        out[prec] = {"ms_per_step": round(ms, 5), "voxels_per_s": voxels / (ms * 1e-3),
+                     "rel_l2_vs_oracle": rel_l2_gpu(f, ref)}
+        pl.close()
+        log(f"64x64 gaussian w12 {prec}: {ms:.4f} ms, rel-L2 vs oracle {out[prec]['rel_l2_vs_oracle']:.3e}")
+    return out
 
 
 def main():
@@ -244,7 +367,12 @@ def main():
     ap.add_argument("--sigma-t", type=float, default=1.25)
     ap.add_argument("--width-t", type=int, default=10)
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="lateral x-modes in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="lateral x-modes in the oracle sample")
+    ap.add_argument("--kahan-compare", choices=["on", "off"], default="on",
+                    help="also time the same workload with compensated (Kahan) summation in the spread")
+    ap.add_argument("--c2-line", choices=["on", "off"], default="on",
+                    help="also time the 64x64 -> 128^3 workload at sigma 2 with Gaussian width-12 windows, FP32 "
+                         "beside FP64, against the oracle")
     ap.add_argument("--batch", choices=["on", "off"], default="on",
                     help="also time the 32-problem batched reconstruction against sequential plans")
     ap.add_argument("--fp64-compare", choices=["on", "off"], default="on",
@@ -363,20 +491,51 @@ def main():
         log(f"{name}: {ops[name]['ms_per_call']:.4f} ms per call")
     result["operators"] = ops
 
+    # the timed image against the FP64 oracle's full image (headline workload only)
+    ref_img, ref_meta = headline_oracle_image() if args.config == 2 else (None, None)
+    if ref_img is not None:
+        result["rel_l2_vs_oracle"] = rel_l2_gpu(out, ref_img, ref_meta["l2_norm_fp64"])
+        log(f"image rel-L2 vs the oracle's full image: {result['rel_l2_vs_oracle']:.3e}")
+
+    if args.kahan_compare == "on" and args.precision == "fp32":
+        # the same workload with compensated (Kahan) summation in the spread
+        pk = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, sigma_xy=args.sigma_xy,
+                  width_xy=args.width_xy, sigma_t=args.sigma_t, width_t=args.width_t, kernel=args.kernel,
+                  precision="fp32_kahan", device=dev)
+        fk = torch.empty_like(out)
+        pk.timing_begin(args.steps + args.warmup)
+        ms_k = _time_calls(lambda: pk.reconstruct(g, out=fk), args.steps, args.warmup, dev)
+        sm_k, nc_k = pk.timing_end()
+        pk.close()
+        result["fp32_kahan"] = {"ms_per_step": round(ms_k, 5), "value": voxels / (ms_k * 1e-3),
+                                "spread_ms": round(sm_k[1] / max(1, nc_k), 5),
+                                "rel_l2_vs_oracle": (rel_l2_gpu(fk, ref_img, ref_meta["l2_norm_fp64"])
+                                                     if ref_img is not None else None),
+                                "rel_l2_vs_fp32": rel_l2_gpu(out, fk.cpu().numpy())}
+        log(f"fp32 with Kahan spread: {ms_k:.4f} ms per step; {result['fp32_kahan']}")
+    del ref_img
+
     if args.fp64_compare == "on" and args.precision != "fp64":
         result["fp64_plain"] = fp64_compare(args, p, g, dev)
 
     if args.batch == "on":
         result["batch"] = bench_batch(args, dev)
 
+    c2_ref = None
     if args.cpu_baseline == "on":
         log("gpu spectrum for the sample check")
         spec = plan.spectrum(g)
         torch.cuda.synchronize(dev)
         spec_np = spec.cpu().numpy().astype(np.complex128)
-        log("cpu baseline (oracle on a sample) ...")
-        result["cpu_baseline"] = cpu_baseline(p, spec_np, args.cpu_sample)
+        log("cpu baseline (oracle on a sample of this workload, full runs of the two small workloads) ...")
+        small = {"16x16_to_32cubed": inputs.config_problem(0), "64x64_to_128cubed": inputs.config_problem(1)}
+        result["cpu_baseline"], imgs = cpu_baseline(p, spec_np, args.cpu_sample, small)
+        c2_ref = imgs["64x64_to_128cubed"]
         log(f"cpu baseline done: {result['cpu_baseline']['seconds_sample']} s sample")
+    if args.c2_line == "on":
+        if c2_ref is None:
+            c2_ref, _ = oracle_full(inputs.config_problem(1), host_cores())
+        result["c2_gaussian12"] = bench_c2_gaussian(args, dev, c2_ref)
     plan.close()
     print(json.dumps(result), flush=True)
 

@@ -143,6 +143,9 @@ typedef struct pat_plan_info {
   int32_t pad0;
   int64_t spread_slots;      /* packed slots of the single-problem spread: groups of up to 4 sensors whose
                                 footprints share no point of a 16 x 4 patch of the oversampled grid */
+  int64_t band_pairs;        /* (x-mode, band bin) pairs inside the per-x-mode ranges of bins the temporal
+                                interpolation reads (at most Nx * band_bins): the pairs the lateral FFT along
+                                y transforms and the interpolation reads from; the others are skipped */
 } pat_plan_info;
 
 /* Fill `desc` with defaults: sigma 2, width 8, Kaiser-Bessel, FP32, window

@@ -47,6 +47,11 @@ __all__ = [
 
 
 def _threads() -> int:
+    """Worker threads of the temporal stage: ORACLE_THREADS if set (the
+    benchmark's single-thread timing), else the CPU count up to 16."""
+    env = os.environ.get("ORACLE_THREADS")
+    if env:
+        return max(1, int(env))
     return max(1, min(16, os.cpu_count() or 1))
 
 

@@ -77,6 +77,7 @@ class PlanInfo(C.Structure):
         ("forward_fused", C.c_int32),
         ("pad0", C.c_int32),
         ("spread_slots", C.c_int64),
+        ("band_pairs", C.c_int64),
     ]
 
 

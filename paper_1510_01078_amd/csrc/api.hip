@@ -393,6 +393,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
       jr[2 * jj + 1] = hi;
     }
   }
+  P->band_pairs = 0;
+  for (int jj = 0; jj < d.nx; ++jj) P->band_pairs += jr[2 * jj + 1] - jr[2 * jj] + 1;
   const size_t o_jr = blob.add(jr.data(), jr.size() * sizeof(int));
   // the same ranges per bin: both ends are non-decreasing in |j|, so the
   // x-modes that hold bin b are J0(b) <= |j| <= J1(b) (J0 > J1: none)
@@ -698,6 +700,7 @@ pat_status pat_plan_get_info(const pat_plan* P, pat_plan_info* info) {
   info->forward_fused = P->forward_fused ? 1 : 0;
   info->pad0 = 0;
   info->spread_slots = P->spread_slots;
+  info->band_pairs = P->band_pairs;
   return PAT_OK;
 }
 

@@ -66,6 +66,7 @@ struct pat_plan {
   size_t ws_bytes = 0;
   int64_t spread_pairs = 0;
   int64_t spread_slots = 0;
+  int64_t band_pairs = 0;   // (x-mode, bin) pairs inside the per-x-mode band ranges
   bool forward_ok = false;  // the forward model's per-column LDS fits the device
   bool forward_fused = false;  // the forward model's x-FFT and interpolation run as one kernel
   double range_xy = 1.0;    // dynamic range of the lateral deconvolution (x times y)

@@ -6,6 +6,9 @@ match within its window error for the chosen oversampling and width, which
 is far below that (frozen bounds below, each with margin over the value
 measured when the bound was set).
 """
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -153,24 +156,52 @@ def test_bitwise_repeatable(dev):
 
 # --------------------------------------------------------------------------
 # headline size (128x128 sensors x 2048 samples -> 256^3) in the benchmark's
-# configuration: spectrum vs the oracle on sampled lateral x-modes, and the
-# image vs the oracle's inverse transform of the GPU spectrum
+# configuration: the whole image against the FP64 oracle's image (written by
+# tests/golden/make_headline_image.py, checked by its SHA-256), for FP32 and
+# for FP32 with compensated spreading; and the spectrum against the oracle on
+# sampled lateral x-modes (the oracle computes those one x-mode at a time)
 # --------------------------------------------------------------------------
 
-def _full_from_half(H, nz):
-    """Natural-order full spectrum from the [j mod Nx][k mod Ny][l = 0..Nz/2]
-    half (F(-K) = conj F(K)); pure re-indexing for the oracle's inverse."""
-    nx, ny, _ = H.shape
-    full = np.zeros((nx, ny, nz), dtype=np.complex128)
-    for l in range(-(nz // 2), nz - nz // 2):
-        if l >= 0:
-            full[:, :, l % nz] = H[:, :, l]
-        else:
-            jj = (-np.arange(nx)) % nx
-            kk = (-np.arange(ny)) % ny
-            full[:, :, l % nz] = np.conj(H[jj][:, kk, -l])
-    # FFT order -> natural order on every axis
-    return np.fft.fftshift(full, axes=(0, 1, 2))
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _headline_oracle_image():
+    meta_path = os.path.join(GOLDEN, "headline_oracle_image.json")
+    with open(meta_path) as fh:
+        meta = json.load(fh)
+    path = os.path.join(GOLDEN, meta["file"])
+    if not os.path.exists(path):
+        pytest.skip(f"{path} missing: run python tests/golden/make_headline_image.py (about 5 CPU-minutes)")
+    h = hashlib.sha256()
+    with open(path, "rb") as fh:
+        for blk in iter(lambda: fh.read(1 << 22), b""):
+            h.update(blk)
+    assert h.hexdigest() == meta["sha256"], "headline oracle image does not match its recorded SHA-256"
+    return np.load(path), meta
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp32_kahan"])
+def test_headline_full_image(dev, precision):
+    from paper_1510_01078_amd import Plan
+    ref32, meta = _headline_oracle_image()
+    p = inputs.config_problem(2)
+    pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision=precision, **TUNED)
+    g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, torch.float32)
+    _say(f"[gpu] headline full image {precision}")
+    f = pl.reconstruct(g)
+    torch.cuda.synchronize()
+    pl.close()
+    ref = torch.from_numpy(ref32).to(dev, torch.float64)
+    d = f.double() - ref
+    e = float(torch.linalg.vector_norm(d) / meta["l2_norm_fp64"])
+    amax = int(torch.argmax(d.abs()))
+    max_abs = float(d.abs().flatten()[amax])
+    where = np.unravel_index(amax, p.shape)
+    _say(f"[gpu] headline {precision}: image rel-L2 vs oracle {e:.3e}; max |error| {max_abs:.3e} at voxel {where} "
+         f"({max_abs / meta['max_abs_fp64']:.3e} of the image's largest magnitude)")
+    assert e <= 1e-5
+    # no localised defect: the worst voxel stays a small fraction of the image's range
+    assert max_abs <= 1e-4 * meta["max_abs_fp64"]
 
 
 def test_headline_size_sampled(dev):
@@ -180,12 +211,12 @@ def test_headline_size_sampled(dev):
     X, Y, Z = p.extent
     pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision="fp32", **TUNED)
     g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, torch.float32)
-    _say("[gpu] headline size: spectrum and image")
+    _say("[gpu] headline size: spectrum on sampled x-modes")
     H = pl.spectrum(g).cpu().numpy().astype(np.complex128)
-    f = pl.reconstruct(g).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     pl.close()
-    rows = np.array([1, 77, 128, 131, 200, 255])          # natural-order x positions
+    # natural-order x positions: the lowest and highest |j| (band edges), and a spread in between
+    rows = np.array([1, 2, 40, 77, 100, 127, 128, 129, 131, 160, 200, 254, 255])
     kx, ky, kz = oracle.lattice(Nx, X), oracle.lattice(Ny, Y), oracle.lattice(Nz, Z)
     G = oracle.stage_lateral(p.xy, p.h, p.g, p.dt, Nx, Ny, X, Y, j_index=rows)
     S = oracle.stage_temporal(G, kx[rows], ky, kz, p.c, p.dt)
@@ -194,8 +225,6 @@ def test_headline_size_sampled(dev):
     ref = np.fft.ifftshift(F, axes=1)[:, :, (lz + Nz // 2) % Nz]
     got = H[(rows - Nx // 2) % Nx]
     e_spec = rel_l2(got, ref)
-    f_from_spec = oracle.inverse(_full_from_half(H, Nz), X, Y, Z)
-    e_img = rel_l2(f, f_from_spec)
-    _say(f"[gpu] headline: spectrum rel-L2 on {len(rows)} x-modes {e_spec:.3e}; image vs inverse of GPU spectrum {e_img:.3e}")
+    per_row = [rel_l2(got[i], ref[i]) for i in range(len(rows)) if np.linalg.norm(ref[i]) > 0]
+    _say(f"[gpu] headline: spectrum rel-L2 on {len(rows)} x-modes {e_spec:.3e}; worst row {max(per_row):.3e}")
     assert e_spec <= 1e-5
-    assert e_img <= 1e-5
