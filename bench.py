@@ -130,24 +130,32 @@ def _time_calls(fn, steps, warmup, dev):
 
 
 def bench_batch(args, dev):
-    """32 uneven problems (Ns ~ U{24..96}, Nt ~ U{512..2048}, 64^3..192^3):
-    one batched call (eight launches), the same call replayed from a HIP
-    graph, and the 32 problems one plan after another."""
+    """32 uneven problems (Ns ~ U{24..96}, Nt ~ U{512..2048}, 64^3..192^3),
+    each with the window setting the autotuner picks for it (oversampling in
+    {1.25, 1.5, 2}, widths in {6, 8, 12}, FP32 within 1e-5 with half of it as
+    margin): one batched call (seven launches), the same call replayed from a
+    HIP graph, and the 32 problems one plan after another with the same
+    settings."""
     import torch
     from paper_1510_01078_amd import Plan, inputs
+    from paper_1510_01078_amd.autotune import Autotuner
     from paper_1510_01078_amd.batch import Batch, problem_dict
     probs = inputs.batched_problems(32, seed=1003)
-    settings = dict(kernel=args.kernel, sigma_xy=args.sigma_xy, width_xy=args.width_xy, sigma_t=args.sigma_t,
-                    width_t=args.width_t)
-    log("batch: building 32 plans (cache-sized groups, then the default single group)")
-    one = Batch([problem_dict(p) for p in probs], precision=args.precision, defaults=settings, device=dev,
-                group_bytes=160 << 20)
-    dtype = one.dtype
+    log("batch: autotuning the window setting of each of the 32 problems")
+    tuner = Autotuner(precision=args.precision, kernel=args.kernel)
+    t0 = time.perf_counter()
+    settings, entries = tuner.tune_batch([problem_dict(p) for p in probs], [p.g for p in probs])
+    t_tune = time.perf_counter() - t0
+    chosen = {}
+    for e in entries:
+        s = e["settings"]
+        k = f"{s['sigma_xy']}/{s['width_xy']} x {s['sigma_t']}/{s['width_t']}"
+        chosen[k] = chosen.get(k, 0) + 1
+    log(f"batch: tuned in {t_tune:.1f} s; settings (lateral sigma/w x temporal sigma/w): {chosen}")
+    b = Batch([problem_dict(p, **st) for p, st in zip(probs, settings)], precision=args.precision, device=dev)
+    dtype = b.dtype
     gs = [torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, dtype) for p in probs]
-    outs = [torch.empty(s, dtype=dtype, device=dev) for s in one.shapes]
-    ms_one = _time_calls(lambda: one.reconstruct(gs, outs), args.steps, args.warmup, dev)
-    one.close()
-    b = Batch([problem_dict(p) for p in probs], precision=args.precision, defaults=settings, device=dev)
+    outs = [torch.empty(s, dtype=dtype, device=dev) for s in b.shapes]
     ms_batch = _time_calls(lambda: b.reconstruct(gs, outs), args.steps, args.warmup, dev)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
@@ -157,7 +165,7 @@ def bench_batch(args, dev):
     b.close()
     del graph
     plans = [Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision=args.precision, device=dev,
-                  **settings) for p in probs]
+                  **st) for p, st in zip(probs, settings)]
 
     def sequential():
         for pl, g, o in zip(plans, gs, outs):
@@ -167,12 +175,14 @@ def bench_batch(args, dev):
         pl.close()
     voxels = float(sum(np.prod(p.shape) for p in probs))
     log(f"batch: {ms_batch:.3f} ms batched ({groups} groups), {ms_graph:.3f} ms graph replay, "
-        f"{ms_one:.3f} ms in 160 MiB cache-sized groups, {ms_seq:.3f} ms sequential")
+        f"{ms_seq:.3f} ms sequential")
     return {"problems": len(probs), "voxels": int(voxels), "groups": groups, "ms_per_batch": round(ms_batch, 4),
-            "ms_per_batch_cache_groups": round(ms_one, 4),
             "ms_per_batch_graph": round(ms_graph, 4), "ms_sequential_plans": round(ms_seq, 4),
             "voxels_per_s": voxels / (ms_batch * 1e-3), "voxels_per_s_graph": voxels / (ms_graph * 1e-3),
-            "speedup_vs_sequential": round(ms_seq / ms_batch, 3)}
+            "speedup_vs_sequential": round(ms_seq / ms_batch, 3),
+            "autotune": {"seconds": round(t_tune, 1), "settings_count": chosen,
+                         "max_rel_err_vs_fp64_reference": max(e["rel_err"] for e in entries),
+                         "reference": "FP64 GPU reconstruction, Kaiser-Bessel sigma 2 width 12"}}
 
 
 def recorded_traffic(args, band_bins):

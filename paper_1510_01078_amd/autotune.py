@@ -3,16 +3,20 @@ whose reconstruction stays within a relative-L2 target.
 
 Accuracy is measured, not predicted: every candidate reconstructs the same
 probe traces and is compared with a high-accuracy FP64 reconstruction on the
-GPU (Kaiser-Bessel, sigma 2, width 12, window error ~1e-8, far below the
-target). Lateral and temporal settings are screened separately (the other
-axis held at the reference setting), then the passing pairs are tried in
-order of their algorithmic cost (band bins times oversampled grid points),
-checked together and timed; the fastest measured pair wins. Results are
-cached by problem shape (sensors, samples, grid, precision, kernel), in
-memory and optionally in a JSON file.
+GPU (Kaiser-Bessel, sigma 2, width 12, whatever kernel is being tuned: its
+window error is about 1e-10, far below the target; the GPU tests check this
+reference against the FP64 oracle). Lateral and temporal settings are screened
+separately (the other axis held at the reference setting: the two window
+errors add, to first order), then the passing pairs are tried in order of
+their algorithmic cost (band bins times oversampled grid points), checked
+together (so a pair whose errors do not simply add is still rejected) and
+timed; the fastest measured pair wins. Results are cached per problem (sensor
+positions and weights, samples, step, speed of sound, grid, extent,
+precision, kernel, target), in memory and optionally in a JSON file.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
@@ -25,11 +29,25 @@ from .plan import Plan
 SIGMAS = (1.25, 1.5, 2.0)
 WIDTHS = (6, 8, 12)
 REFERENCE = dict(sigma_xy=2.0, width_xy=12, sigma_t=2.0, width_t=12)
+REFERENCE_KERNEL = "kaiser_bessel"
 
 
 def _rel(a, b):
     import torch
     return float(torch.linalg.vector_norm((a.double() - b).reshape(-1)) / torch.linalg.vector_norm(b.reshape(-1)))
+
+
+def problem_key(problem, precision, kernel, target):
+    """Cache key of one problem: every input the chosen setting depends on."""
+    xy = np.ascontiguousarray(problem["sensor_xy"], dtype=np.float64).reshape(-1, 2)
+    h = problem.get("sensor_h")
+    dig = hashlib.sha1(xy.tobytes())
+    if h is not None:
+        dig.update(np.ascontiguousarray(h, dtype=np.float64).tobytes())
+    shape = "x".join(str(int(v)) for v in problem["shape"])
+    extent = ",".join(repr(float(v)) for v in problem["extent"])
+    return (f"{xy.shape[0]}x{int(problem['n_t'])}->{shape}:ext={extent}:dt={float(problem['dt'])!r}:"
+            f"c={float(problem['c'])!r}:sensors={dig.hexdigest()[:16]}:{precision}:{kernel}:target={target!r}")
 
 
 class Autotuner:
@@ -47,12 +65,23 @@ class Autotuner:
             with open(cache_path) as fh:
                 self.cache = json.load(fh)
 
-    def key(self, m, nt, shape):
-        return f"{m}x{nt}->{shape[0]}x{shape[1]}x{shape[2]}:{self.precision}:{self.kernel}"
+    def key(self, problem):
+        return problem_key(problem, self.precision, self.kernel, self.target)
 
-    def _plan(self, p, precision, settings):
+    def _plan(self, p, precision, settings, kernel=None):
         return Plan(p["sensor_xy"], p["n_t"], p["dt"], p["c"], p["shape"], p["extent"], sensor_h=p.get("sensor_h"),
-                    precision=precision, kernel=self.kernel, **settings)
+                    precision=precision, kernel=kernel or self.kernel, **settings)
+
+    def reference(self, problem, probe):
+        """The tuner's accuracy reference: FP64 reconstruction of `probe` at
+        REFERENCE / REFERENCE_KERNEL (a device tensor)."""
+        import torch
+        g64 = torch.as_tensor(np.ascontiguousarray(probe), dtype=torch.float64).cuda()
+        ref_plan = self._plan(problem, "fp64", REFERENCE, kernel=REFERENCE_KERNEL)
+        ref = ref_plan.reconstruct(g64)
+        torch.cuda.synchronize()
+        ref_plan.close()
+        return ref
 
     def tune(self, problem, probe):
         """problem: dict as for Batch (sensor_xy, n_t, dt, c, shape, extent,
@@ -61,15 +90,11 @@ class Autotuner:
         their measured relative error and time per call, and every setting
         evaluated with its error."""
         import torch
-        m = int(np.asarray(problem["sensor_xy"]).reshape(-1, 2).shape[0])
-        k = self.key(m, int(problem["n_t"]), tuple(problem["shape"]))
+        k = self.key(problem)
         if k in self.cache:
             return self.cache[k]
         g64 = torch.as_tensor(np.ascontiguousarray(probe), dtype=torch.float64).cuda()
-        ref_plan = self._plan(problem, "fp64", REFERENCE)
-        ref = ref_plan.reconstruct(g64)
-        torch.cuda.synchronize()
-        ref_plan.close()
+        ref = self.reference(problem, probe)
         dt_work = torch.float64 if self.precision == "fp64" else torch.float32
         g = g64.to(dt_work)
         limit = self.target * self.margin
@@ -134,3 +159,11 @@ class Autotuner:
             with open(self.cache_path, "w") as fh:
                 json.dump(self.cache, fh, indent=1, sort_keys=True)
         return best
+
+    def tune_batch(self, problems, probes):
+        """tune() for every problem of a batch: the list of chosen settings
+        (dicts of sigma_xy, width_xy, sigma_t, width_t, kernel) and the list
+        of cache entries."""
+        entries = [self.tune(p, g) for p, g in zip(problems, probes)]
+        settings = [dict(e["settings"], kernel=self.kernel) for e in entries]
+        return settings, entries

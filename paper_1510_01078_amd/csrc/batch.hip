@@ -128,35 +128,38 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     const int gx2 = (d.n_y + rows - 1) / rows;
     a2[p] = patk::FftXBA{A, patk::as_view(d.f_nx), d.n_y, d.Nx, rows, gx2, Bw};
     pre[2][p + 1] = gx2 * d.nb;
-    lds[2] = std::max(lds[2], size_t(rows) * patk::lseq(d.n_x) * c);
+    lds[2] = std::max(lds[2], (size_t(rows) * patk::lseq(d.n_x) + d.n_x) * c);
     // stage 3: FFT along y with deconvolution
     const int bins = patk::fft_batch<T>(d.n_y, cfg.threads, cfg.cap);
     if (bins * d.n_y > kFft || bins * d.Ny > kFft) return PAT_ERR_UNSUPPORTED;
     const int gx3 = (d.nb + bins - 1) / bins;
-    a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A};
+    a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A, d.jrange};
     pre[3][p + 1] = gx3 * d.Nx;
-    lds[3] = std::max(lds[3], size_t(bins) * patk::lseq(d.n_y) * c);
+    lds[3] = std::max(lds[3], (size_t(bins) * patk::lseq(d.n_y) + d.n_y) * c);
     // stage 4: temporal interpolation and weight (image-ready spectrum) fused
     // with the inverse transform along x
     const int lcx = patk::fft_batch<T>(d.Nx, icfg.threads, icfg.cap);
     const int gx5 = (Lh + lcx - 1) / lcx;
-    a4[p] = patk::GatherBA{A, d.hcoef, d.nb, d.b_lo, d.Nx, d.Ny, d.Nz, d.w_t, d.hdeg,
+    int wt_ct = 0;
+    for (int t : patk::kBatchTaps)
+      if (d.w_t == t && d.w_t * (d.hdeg + 1) <= patk::kMaxTapCoefs) wt_ct = t;
+    a4[p] = patk::GatherBA{A, d.hcoef, d.nb, d.b_lo, d.Nx, d.Ny, d.Nz, d.w_t, d.hdeg, wt_ct, 0,
                            d.s_per_k, d.kxu, d.kyu, d.kzu, d.two_c, d.n0_over_nt, d.inv_vol, Bw,
                            patk::as_view(d.f_Nx), lcx, gx5};
     pre[4][p + 1] = gx5 * d.Ny;
-    lds[4] = std::max(lds[4], size_t(lcx) * patk::lseq(d.Nx) * c);
+    lds[4] = std::max(lds[4], (size_t(lcx) * patk::lseq(d.Nx) + d.Nx) * c);
     // stage 5: inverse transform along y (in place on the spectrum)
     const int lcy = patk::fft_batch<T>(d.Ny, icfg.threads, icfg.cap);
     const int gx6 = (Lh + lcy - 1) / lcy;
     a5[p] = patk::CfftBA{Bw, patk::as_view(d.f_Ny), d.Ny, Lh, lcy, gx6};
     pre[5][p + 1] = gx6 * d.Nx;
-    lds[5] = std::max(lds[5], size_t(lcy) * patk::lseq(d.Ny) * c);
+    lds[5] = std::max(lds[5], (size_t(lcy) * patk::lseq(d.Ny) + d.Ny) * c);
     // stage 6: complex-to-real along z into the caller's image
     const int rz = patk::fft_batch<T>(d.Nz, icfg.threads, icfg.cap);
     const long long nrows = (long long)d.Nx * d.Ny;
     a6[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
     pre[6][p + 1] = int((nrows + rz - 1) / rz);
-    lds[6] = std::max(lds[6], size_t(rz) * patk::lseq(d.Nz) * c);
+    lds[6] = std::max(lds[6], (size_t(rz) * patk::lseq(d.Nz) + d.Nz) * c);
   }
   for (auto& v : pre) {
     for (int p = 0; p < P; ++p) {
@@ -185,11 +188,6 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
   }
   unsigned char* tb = static_cast<unsigned char*>(G.tables);
   const bool kahan = B->plans[0]->dp.kahan;
-  int wt = G.members.empty() ? 0 : B->plans[G.members[0]]->dp.w_t;
-  for (int m : G.members) {
-    const patk::DevPlan& d = B->plans[m]->dp;
-    if (d.w_t != wt || d.w_t * (d.hdeg + 1) > patk::kMaxTapCoefs) wt = 0;
-  }
   for (int i = 0; i < kStages; ++i) {
     G.st[i].args = tb + oa[i];
     G.st[i].prefix = reinterpret_cast<const int*>(tb + op[i]);
@@ -198,7 +196,6 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     G.st[i].lds = lds[i];
     G.st[i].grid = kPersistentBlocks;
     G.st[i].kahan = kahan;
-    G.st[i].wt = wt;
   }
   return PAT_OK;
 }

@@ -201,9 +201,8 @@ __device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int 
   const int bstride = lseq(Nx);
   const int l0 = bx * lchunk;
   const int nl = min(lchunk, Lh - l0);
-  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  cx<T>* twl = buf + lchunk * bstride;  // the twiddles go to LDS behind the rows
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   const FastDiv div_nl(nl);
   for (int q = tid; q < nl * Nx; q += nthr) {
@@ -217,7 +216,7 @@ __device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int 
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nl, twl, tid);
   else
-    fft_group<T, true>(buf, fd, nl, bstride, tid, nthr, wm);
+    fft_group<T, true>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
@@ -500,33 +499,47 @@ hipError_t launch_scatter(const DevPlan& p, const void* Dh, void* Gh, int deriv,
 
 // Batched form of the reconstruction's interpolation (image-ready spectrum)
 // fused with the inverse transform along x, each work item as in the
-// single-problem launch (same arithmetic, same bits; the runtime-planned
-// transform, as the problems' lengths differ). WT > 0: every problem of the
-// group has WT taps; a work-group restages the tap coefficients in LDS when
-// its next work item belongs to another problem.
+// single-problem launch (same arithmetic; the runtime-planned transform, as
+// the problems' lengths differ). Each problem runs with its own tap count at
+// compile time when it is one of kBatchTaps (else the runtime-tap form); a
+// work-group restages the tap coefficients in LDS when its next work item
+// belongs to another problem.
 template <typename T, int WT>
+__device__ __forceinline__ void gather_batch_item(const GatherBA& a, T* coefs, int& staged, int p, int local) {
+  if constexpr (WT > 0) {
+    if (p != staged) {  // visible after the body's first barrier
+      stage_tap_coefs<T, WT>(coefs, static_cast<const T*>(a.hcoef), a.deg);
+      staged = p;
+    }
+  }
+  const int kk = local / a.gx;
+  gather_x_body<T, MODE_IMAGE, WT, 0>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k,
+                                      a.kxu, a.kyu, a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg,
+                                      static_cast<const T*>(a.hcoef), a.lchunk, view_desc<T>(a.fd), 0,
+                                      static_cast<cx<T>*>(a.Fh), local - kk * a.gx, kk, coefs);
+}
+
+template <typename T>
 __global__ __launch_bounds__(kFftThreads) void k_gather_batch(const GatherBA* __restrict__ args,
                                                             const int* __restrict__ prefix, int nprob, int total,
                                                             BatchIO io) {
   __shared__ BatchMeta<GatherBA> meta;
-  __shared__ T coefs[WT > 0 ? kMaxTapCoefs : 1];
+  __shared__ T coefs[kMaxTapCoefs];
   batch_meta_load(meta, args, prefix, nprob);
   int staged = -1;
   for (int w = blockIdx.x; w < total; w += gridDim.x) {
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const GatherBA a = batch_args(meta, p);
-    if constexpr (WT > 0) {
-      if (p != staged) {  // visible after the body's first barrier
-        stage_tap_coefs<T, WT>(coefs, static_cast<const T*>(a.hcoef), a.deg);
-        staged = p;
-      }
-    }
     const int local = w - meta.prefix[p];
-    const int kk = local / a.gx;
-    gather_x_body<T, MODE_IMAGE, WT, 0>(static_cast<const cx<T>*>(a.Gh), a.nb, a.b_lo, a.Nx, a.Ny, a.Nz, a.s_per_k,
-                                        a.kxu, a.kyu, a.kzu, a.two_c, a.n0_over_nt, a.scale, a.wt, a.deg,
-                                        static_cast<const T*>(a.hcoef), a.lchunk, view_desc<T>(a.fd), 0,
-                                        static_cast<cx<T>*>(a.Fh), local - kk * a.gx, kk, coefs);
+    static_assert(kBatchTaps[0] == 6 && kBatchTaps[1] == 8 && kBatchTaps[2] == 10 && kBatchTaps[3] == 12,
+                  "tap instantiations");
+    switch (a.wt_ct) {
+      case 6: gather_batch_item<T, 6>(a, coefs, staged, p, local); break;
+      case 8: gather_batch_item<T, 8>(a, coefs, staged, p, local); break;
+      case 10: gather_batch_item<T, 10>(a, coefs, staged, p, local); break;
+      case 12: gather_batch_item<T, 12>(a, coefs, staged, p, local); break;
+      default: gather_batch_item<T, 0>(a, coefs, staged, p, local); break;
+    }
     __syncthreads();
   }
 }
@@ -534,16 +547,11 @@ __global__ __launch_bounds__(kFftThreads) void k_gather_batch(const GatherBA* __
 template <typename T>
 hipError_t launch_gather_batch(const BatchStage& st, const BatchIO& io, hipStream_t s) {
   if (st.total <= 0) return hipSuccess;
-  auto go = [&](auto c) {
-    constexpr int WT = decltype(c)::value;
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T, WT>), st.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_gather_batch<T, WT>), dim3(batch_grid(st)), dim3(256), st.lds, s,
-                       static_cast<const GatherBA*>(st.args), st.prefix, st.nprob, st.total, io);
-    return hipGetLastError();
-  };
-  if (st.wt == 0) return go(std::integral_constant<int, 0>{});
-  return wt_pick(st.wt, go);
+  hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_gather_batch<T>), st.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_gather_batch<T>), dim3(batch_grid(st)), dim3(256), st.lds, s,
+                     static_cast<const GatherBA*>(st.args), st.prefix, st.nprob, st.total, io);
+  return hipGetLastError();
 }
 
 #define PATK_INST(T)                                                                     \

@@ -35,14 +35,13 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
         const int jj = div_nl(q);
         buf[(q - jj * nl) * bstride + lpos(jj)] = v;
       });
-  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  cx<T>* twl = buf + lchunk * bstride;  // the twiddles go to LDS behind the rows
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
   else
-    fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
+    fft_group<T, INV>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Nx, tid, nthr,
@@ -87,14 +86,13 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
         const int kk = div_nl(q);
         buf[(q - kk * nl) * bstride + lpos(kk)] = v;
       });
-  cx<T>* twl = buf + lchunk * bstride;  // compile-time form: twiddles in LDS behind the rows
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  cx<T>* twl = buf + lchunk * bstride;  // the twiddles go to LDS behind the rows
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
   else
-    fft_group<T, INV>(buf, fd, nl, bstride, tid, nthr, wm);
+    fft_group<T, INV>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nl * Ny, tid, nthr,
@@ -154,13 +152,12 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
         }
       });
   cx<T>* twl = buf + rows * bstride;
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, np, twl, tid);
   else
-    fft_group<T, true>(buf, fd, np, bstride, tid, nthr, wm);
+    fft_group<T, true>(buf, lds_twiddles(fd, twl), np, bstride, tid, nthr, wm);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr,
@@ -199,13 +196,12 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
         buf[r * bstride + lpos(q - r * Nz)] = cx<T>{v, T(0)};
       });
   cx<T>* twl = buf + rows * bstride;
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), false>(buf, nr, twl, tid);
   else
-    fft_lds<T, kFftMaxV, false, false>(buf, fd, nr, bstride, tid, nthr);
+    fft_lds<T, kFftMaxV, false, false>(buf, lds_twiddles(fd, twl), nr, bstride, tid, nthr);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nr * Lh, tid, nthr,

@@ -177,9 +177,11 @@ struct FftXBA {
 };
 struct FftYBA {
   const void* V; const void* dcx; const void* dcy; FftView fd; int nb, Nx, Ny, bins, gx; void* Gh;
+  const int* jrange;  // per x-mode band range (bin groups outside it are skipped)
 };
 struct GatherBA {  // the gather fused with the inverse transform along x
   const void* Gh; const void* hcoef; int nb, b_lo, Nx, Ny, Nz, wt, deg;
+  int wt_ct, pad;  // compile-time tap count to run (kBatchTaps member equal to wt, else 0: runtime taps)
   double s_per_k, kxu, kyu, kzu, two_c, n0_over_nt, scale; void* Fh;
   FftView fd; int lchunk, gx;  // x transform (length Nx), z modes per group, groups along z
 };
@@ -202,8 +204,11 @@ struct BatchStage {
   size_t lds = 0;
   int grid = 0;
   bool kahan = false;  // spread with compensated summation
-  int wt = 0;          // temporal taps shared by every problem of the group (0: they differ)
 };
+
+// tap counts the batched gather instantiates at compile time (each problem
+// runs its own; other counts take the runtime-tap form)
+constexpr int kBatchTaps[4] = {6, 8, 10, 12};
 
 // temporal tap polynomials staged in LDS: at most 16 taps of degree <= 24
 constexpr int kMaxTapCoefs = 16 * 25;

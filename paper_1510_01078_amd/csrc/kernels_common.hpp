@@ -80,6 +80,15 @@ __device__ __forceinline__ void fft_group(cx<T>* buf, const FftDesc<T>& fd, int 
   }
 }
 
+// The same transform with its twiddle table read from a copy in LDS (every
+// pass reads the table between two barriers; from LDS the reads cost a few
+// dozen cycles instead of a cache round trip).
+template <typename T>
+__device__ __forceinline__ FftDesc<T> lds_twiddles(FftDesc<T> fd, const cx<T>* twl) {
+  fd.tw = twl;
+  return fd;
+}
+
 // Allow a kernel more than the default dynamic LDS when a launch needs it.
 // The largest size granted per (kernel, device) is remembered in a fixed
 // table, so repeated launches (also inside a stream capture) make no runtime

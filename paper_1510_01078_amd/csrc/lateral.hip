@@ -31,15 +31,14 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
         const int r = div_nx(q);
         buf[r * bstride + lpos(q - r * n_x)] = v;
       });
-  // compile-time form: the twiddles go to LDS behind the rows (every pass reads them)
+  // the twiddles go to LDS behind the rows (every pass reads them)
   cx<T>* twl = buf + rows * bstride;
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nr, twl, tid);
   else
-    fft_group<T, false>(buf, fd, nr, bstride, tid, nthr, wm);
+    fft_group<T, false>(buf, lds_twiddles(fd, twl), nr, bstride, tid, nthr, wm);
   __syncthreads();
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
   staged_copy<kFftMaxV>(
@@ -117,13 +116,12 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
         buf[bi * bstride + lpos(q - bi * n_y)] = v;
       });
   cx<T>* twl = buf + bins * bstride;
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nbc, twl, tid);
   else
-    fft_group<T, false>(buf, fd, nbc, bstride, tid, nthr, wm);
+    fft_group<T, false>(buf, lds_twiddles(fd, twl), nbc, bstride, tid, nthr, wm);
   __syncthreads();
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
@@ -216,13 +214,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
         buf[(q - kk * nbc) * bstride + lpos(k < 0 ? k + n_y : k)] = v;
       });
   cx<T>* twl = buf + bins * bstride;
-  if constexpr (NCT > 0)
-    for (int t = tid; t < NCT; t += nthr) twl[t] = fd.tw[t];
+  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
     fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), true>(buf, nbc, twl, tid);
   else
-    fft_lds<T, kFftMaxV, true, false>(buf, fd, nbc, bstride, tid, nthr);
+    fft_lds<T, kFftMaxV, true, false>(buf, lds_twiddles(fd, twl), nbc, bstride, tid, nthr);
   __syncthreads();
   staged_copy<kFftMaxV>(
       nbc * n_y, tid, nthr,
@@ -345,7 +342,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __res
     const int by = local / a.gx;
     fft_y_body<T>(static_cast<const cx<T>*>(a.V), a.nb, a.Nx, a.Ny, a.bins, static_cast<const T*>(a.dcx),
                   static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, local - by * a.gx,
-                  by);
+                  by, a.jrange);
     __syncthreads();
   }
 }

@@ -3,7 +3,9 @@ whose error and cost depend on the window settings in a known way: settings
 beyond the error limit are rejected, refused settings (PAT_ERR_UNSUPPORTED)
 are recorded and skipped, the cheapest passing pair is chosen when time
 follows cost, nothing passing falls back to the reference setting, and
-results are cached by problem shape in memory and in the JSON file.
+results are cached per problem in memory and in the JSON file, under a key
+that changes with the sensor positions, the sampling step, the speed of sound
+and the extent.
 The GPU test (tests/test_gpu_autotune.py) runs the same code on real plans.
 """
 import json
@@ -67,7 +69,7 @@ def cpu_tuner(monkeypatch):
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     refuse = set()
 
-    def make(self, p, precision, settings):
+    def make(self, p, precision, settings, kernel=None):
         return FakePlan(precision, settings, refuse)
 
     monkeypatch.setattr(at.Autotuner, "_plan", make)
@@ -120,7 +122,19 @@ def test_cache_in_memory_and_file(cpu_tuner, tmp_path):
     again = t.tune(_problem(), np.zeros((6, 16)))
     assert again is first and FakePlan.made == made  # served from memory, no plan built
     stored = json.loads(path.read_text())
-    assert t.key(6, 16, (4, 4, 4)) in stored
+    assert t.key(_problem()) in stored
     t2 = at.Autotuner(target=1e-5, cache_path=str(path))
     assert t2.tune(_problem(), np.zeros((6, 16)))["settings"] == first["settings"]
     assert FakePlan.made == made                     # served from the file
+
+
+def test_key_separates_problems_of_one_shape():
+    base = _problem()
+    k0 = at.problem_key(base, "fp32", "kaiser_bessel", 1e-5)
+    moved = dict(base, sensor_xy=base["sensor_xy"] + 1e-6)
+    for other in (moved, dict(base, dt=2e-8), dict(base, c=1540.0), dict(base, extent=(2e-3, 1e-3, 1e-3)),
+                  dict(base, sensor_h=np.ones(6))):
+        assert at.problem_key(other, "fp32", "kaiser_bessel", 1e-5) != k0
+    assert at.problem_key(base, "fp32", "gaussian", 1e-5) != k0
+    assert at.problem_key(base, "fp32", "kaiser_bessel", 1e-6) != k0
+    assert at.problem_key(dict(base), "fp32", "kaiser_bessel", 1e-5) == k0
