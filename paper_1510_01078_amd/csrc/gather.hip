@@ -527,7 +527,8 @@ __global__ __launch_bounds__(kFftThreads) void k_gather_batch(const GatherBA* __
   __shared__ T coefs[kMaxTapCoefs];
   batch_meta_load(meta, args, prefix, nprob);
   int staged = -1;
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const GatherBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];

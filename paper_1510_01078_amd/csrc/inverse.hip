@@ -294,7 +294,8 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* 
                                                                   BatchIO io) {
   __shared__ BatchMeta<CfftBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const CfftBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __rest
                                                              BatchIO io) {
   __shared__ BatchMeta<C2rBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const C2rBA a = batch_args(meta, p);
     c2r_z_body<T>(static_cast<const cx<T>*>(a.F), a.nrows, a.rows, view_desc<T>(a.fd), static_cast<T*>(io.out[p]), 0,

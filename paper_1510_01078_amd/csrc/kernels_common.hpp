@@ -199,6 +199,19 @@ __device__ __forceinline__ int batch_locate(const int* prefix, int nprob, int w)
   return lo;
 }
 
+// Work item of a batched launch's slot L = blockIdx.x + i * gridDim.x (the
+// i-th pass of a persistent grid). The hardware places work-groups on the 8
+// XCDs round-robin, so with a grid that is a multiple of 8 slots L and L + 8
+// share an XCD; items 2m and 2m + 1 (neighbouring blocks of one problem,
+// which write the two halves of the same 128-byte lines) are given such a
+// pair of slots, so that XCD's L2 merges the halves. A bijection on
+// [0, total): the last total mod 16 items keep their slots.
+__device__ __forceinline__ int batch_item(int L, int total) {
+  if (L >= (total & ~15)) return L;
+  const int r = L & 15;
+  return (L & ~15) + 2 * (r & 7) + (r >> 3);
+}
+
 // Grid of a batched launch: one block per work item, or `st.grid` blocks
 // striding over the items.
 static inline unsigned batch_grid(const BatchStage& st) {

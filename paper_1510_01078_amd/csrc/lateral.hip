@@ -318,7 +318,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __res
                                                              BatchIO io) {
   __shared__ BatchMeta<FftXBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const FftXBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];
@@ -335,7 +336,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __res
                                                              BatchIO io) {
   __shared__ BatchMeta<FftYBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const FftYBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];

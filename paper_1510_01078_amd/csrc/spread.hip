@@ -186,7 +186,8 @@ __global__ __launch_bounds__(64) void k_spread_batch(const SpreadBA* __restrict_
                                                      const int* __restrict__ prefix, int nprob, int total, BatchIO io) {
   __shared__ BatchMeta<SpreadBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const SpreadBA a = batch_args(meta, p);
     spread_slot_body<T, KAHAN>(static_cast<const cx<T>*>(a.Gt), a.nb, a.slot_off, a.slot_sens,

@@ -168,7 +168,8 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const Tempo
                                                                      BatchIO io) {
   __shared__ BatchMeta<TemporalBA> meta;
   batch_meta_load(meta, args, prefix, nprob);
-  for (int w = blockIdx.x; w < total; w += gridDim.x) {
+  for (int slot = blockIdx.x; slot < total; slot += gridDim.x) {
+    const int w = batch_item(slot, total);
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const TemporalBA a = batch_args(meta, p);
     temporal_body<T>(static_cast<const T*>(io.in[p]), a.M, a.Nt, a.n0, static_cast<const T*>(a.hw),
