@@ -185,6 +185,54 @@ def bench_batch(args, dev):
                          "reference": "FP64 GPU reconstruction, Kaiser-Bessel sigma 2 width 12"}}
 
 
+def bench_differentiable(args, dev):
+    """The differentiable workload (96x96 warped sensors, 1536 samples at
+    40 MHz, 8 balls, 192^3) at the benchmark's window setting: time per call
+    of the forward model, its adjoint and one position derivative; one
+    autograd step (forward, then the gradients with respect to the image and
+    to all sensor positions); 20 power-iteration steps for ||A||^2 and 10
+    Landweber iterations on the phantom's traces."""
+    import torch
+    from paper_1510_01078_amd import Plan, inputs
+    from paper_1510_01078_amd.autograd import forward_model
+    from paper_1510_01078_amd.iterative import landweber, operator_norm_sq
+    q = inputs.config_problem(4)
+    pl = Plan(q.xy, q.nt, q.dt, q.c, q.shape, q.extent, sensor_h=q.h, sigma_xy=args.sigma_xy,
+              width_xy=args.width_xy, sigma_t=args.sigma_t, width_t=args.width_t, kernel=args.kernel,
+              precision=args.precision, device=dev)
+    f0 = torch.from_numpy(inputs.voxelise_balls(q.balls, *q.shape, *q.extent)).to(dev, pl.dtype)
+    g = torch.from_numpy(np.ascontiguousarray(q.g)).to(dev, pl.dtype)
+    gout = torch.empty_like(g)
+    fout = torch.empty_like(f0)
+    out = {"workload": WORKLOADS[4], "sensors": q.m, "samples": q.nt, "grid": list(q.shape)}
+    out["forward_ms"] = round(_time_calls(lambda: pl.forward(f0, out=gout), args.steps, args.warmup, dev), 5)
+    out["adjoint_ms"] = round(_time_calls(lambda: pl.adjoint(g, out=fout), args.steps, args.warmup, dev), 5)
+    out["forward_dx_ms"] = round(_time_calls(lambda: pl.forward_dxy(f0, 0, out=gout), args.steps, args.warmup,
+                                             dev), 5)
+    w = torch.randn(g.shape, generator=torch.Generator(device=dev).manual_seed(5), device=dev, dtype=pl.dtype)
+    xy = torch.from_numpy(q.xy.copy())
+
+    def autograd_step():
+        f = f0.clone().requires_grad_(True)
+        x = xy.clone().requires_grad_(True)
+        loss = (forward_model(f, x, pl) * w).sum()
+        return torch.autograd.grad(loss, (f, x))
+
+    out["autograd_step_ms"] = round(_time_calls(autograd_step, max(1, args.steps // 4), 1, dev), 5)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    tau = 1.0 / operator_norm_sq(pl, f0 + 0.01, 20)
+    fl, res, _ = landweber(pl, g, iters=10, tau=tau)
+    torch.cuda.synchronize(dev)
+    out["power20_landweber10_ms"] = round(1000.0 * (time.perf_counter() - t0), 3)
+    out["landweber_residual"] = [res[0], res[-1]]
+    out["tau"] = tau
+    pl.close()
+    log(f"differentiable: forward {out['forward_ms']} ms, adjoint {out['adjoint_ms']} ms, autograd step "
+        f"{out['autograd_step_ms']} ms, 20 power steps + 10 Landweber {out['power20_landweber10_ms']} ms")
+    return out
+
+
 def recorded_traffic(args, band_bins):
     """HBM bytes per spread launch from the committed FETCH_SIZE/WRITE_SIZE
     summary, or None when no record matches this workload or the spread
@@ -380,6 +428,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=24, help="lateral x-modes in the oracle sample")
     ap.add_argument("--kahan-compare", choices=["on", "off"], default="on",
                     help="also time the same workload with compensated (Kahan) summation in the spread")
+    ap.add_argument("--differentiable", choices=["on", "off"], default="on",
+                    help="also time the forward model, adjoint, autograd and Landweber on the 96x96 -> 192^3 workload")
     ap.add_argument("--c2-line", choices=["on", "off"], default="on",
                     help="also time the 64x64 -> 128^3 workload at sigma 2 with Gaussian width-12 windows, FP32 "
                          "beside FP64, against the oracle")
@@ -530,6 +580,9 @@ def main():
 
     if args.batch == "on":
         result["batch"] = bench_batch(args, dev)
+
+    if args.differentiable == "on" and args.precision != "fp64":
+        result["differentiable"] = bench_differentiable(args, dev)
 
     c2_ref = None
     if args.cpu_baseline == "on":

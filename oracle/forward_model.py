@@ -77,9 +77,12 @@ def image_spectrum(f, extent):
     return _nyquist_zero(D)
 
 
-def forward(f, xy, nt, dt, c, extent, deriv=None):
+def forward(f, xy, nt, dt, c, extent, deriv=None, n_index=None):
     """(A f)[m, n] (module docstring); deriv = "x" or "y" gives the
-    derivative of each trace with respect to its sensor's x or y.
+    derivative of each trace with respect to its sensor's x or y. With
+    n_index only the samples t_n = n dt for those n, as columns in that
+    order (each output is its own sum, so a sample of them equals the same
+    entries of the full result).
 
     Per lateral mode column: P[k, n] = sum_l D[j,k,l] cos(c|K| t_n); then the
     sensor sum exp(i Kx x_m) sum_k exp(i Ky y_m) P[k, n] as matrix products.
@@ -91,11 +94,11 @@ def forward(f, xy, nt, dt, c, extent, deriv=None):
     V = X * Y * Z
     D = image_spectrum(f, extent)
     kx, ky, kz = lattice(nx, X), lattice(ny, Y), lattice(nz, Z)
-    t = np.arange(nt) * dt
+    t = (np.arange(nt) if n_index is None else np.asarray(n_index)) * dt
     ey = np.exp(1j * np.outer(xy[:, 1], ky))                 # [M, ny]
     if deriv == "y":
         ey = ey * (1j * ky)[None, :]
-    g = np.zeros((xy.shape[0], nt))
+    g = np.zeros((xy.shape[0], len(t)))
     for j in range(nx):
         kabs = np.sqrt(kx[j] ** 2 + ky[:, None] ** 2 + kz[None, :] ** 2)      # [ny, nz]
         cosk = np.cos(c * kabs[:, :, None] * t[None, None, :])                # [ny, nz, nt]

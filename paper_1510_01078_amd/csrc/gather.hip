@@ -34,6 +34,18 @@ __device__ __forceinline__ TapPoint tap_point(double Kabs, double s_per_k, doubl
   return tp;
 }
 
+// |K| and 1/|K| of a lattice point from one reciprocal square root (no FP64
+// division for the weight W); K = 0 keeps |K| = 0. The interpolation and its
+// transpose both take |K| from here, so they choose the same first tap bin
+// and weights for every lattice point, bit for bit: where s = |K| c dt n_t /
+// (2 pi) is an integer, two roundings of |K| could otherwise pick bases one
+// bin apart (both valid interpolations, but no longer exact transposes).
+__device__ __forceinline__ double lattice_kabs(double Kx, double Ky, double Kz, double& rK) {
+  const double K2 = Kx * Kx + Ky * Ky + Kz * Kz;
+  rK = K2 > 0.0 ? rsqrt(K2) : 0.0;
+  return K2 * rK;
+}
+
 // Tap weight t of the temporal window at argument y (Horner on the per-tap
 // polynomial fitted at plan time).
 template <typename T>
@@ -101,11 +113,8 @@ __device__ __forceinline__ cx<T> gather_point(const cx<T>* __restrict__ Gh, int 
   const int j = jj < Nx / 2 ? jj : jj - Nx;
   const int k = kk < Ny / 2 ? kk : kk - Ny;
   const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
-  // |K| and 1/|K| from one reciprocal square root (no FP64 division for W);
-  // K = 0 (the adjoint's l = 0 plane) keeps |K| = 0
-  const double K2 = Kx * Kx + Ky * Ky + Kz * Kz;
-  const double rK = K2 > 0.0 ? rsqrt(K2) : 0.0;
-  const double Kabs = K2 * rK;
+  double rK;
+  const double Kabs = lattice_kabs(Kx, Ky, Kz, rK);
   const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
   const T y = T(tp.y);
   const cx<T>* src = Gh + col * nb + tp.base;
@@ -373,7 +382,8 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, i
     const int j = jj < Nx / 2 ? jj : jj - Nx;
     const int k = kk < Ny / 2 ? kk : kk - Ny;
     const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
-    const double Kabs = sqrt(Kx * Kx + Ky * Ky + Kz * Kz);
+    double rK;
+    const double Kabs = lattice_kabs(Kx, Ky, Kz, rK);
     const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
     const T y = T(tp.y);
     {

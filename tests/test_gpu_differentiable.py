@@ -1,0 +1,243 @@
+"""The differentiable workload at full size: 96 x 96 warped sensors on a
+20 mm plane, 1536 samples at 40 MHz, 8 balls, 192^3 output, FP32 (the
+forward model pat_forward, its adjoint pat_adjoint and the position
+derivatives pat_forward_dxy, through the C ABI and the autograd wrapper).
+
+Checks, each at the full size unless said otherwise:
+
+* the forward model of a lattice plane wave equals the wave equation's
+  standing wave cos(K0x x_m + K0y y_m + phi) cos(c|K0| t_n) at all 9216
+  sensors and 1536 samples, and its position derivatives equal the closed
+  form, within 1e-5 (Section 2: the initial value problem);
+* the forward model of the phantom against the FP64 oracle on sampled
+  outputs (a subset of sensors at a subset of sample times; the oracle
+  computes each output as its own sum), within 1e-5;
+* <A f, g> = <f, A* g> for the GPU pair (relative 1e-12 in FP64, 1e-5 in
+  FP32);
+* the autograd gradients of L = <w, A f> with respect to the image and to
+  all 9216 sensor positions: against the FP64 oracle gradient on sampled
+  sensors (w is nonzero only on a subset of sample times, so the oracle
+  sums only those), within 1e-5, and against the same gradient from the
+  FP64 GPU form for every sensor;
+* 10 Landweber iterations with tau = 1/||A||^2 from 20 power-iteration
+  steps: the residual never increases, and the FP32 iterate agrees with the
+  FP64 GPU iterate (same tau) within 1e-4 (ten chained FP32 applications of
+  A and A*);
+* on the 16^3 grid with 8 x 8 sensors and 64 samples, in FP64: the image
+  and position gradients against central differences with h = 1e-6
+  (pressure units for the image, metres for the positions): the loss is
+  linear in the image, so there the difference quotient carries only the
+  cancellation error eps |L| / h of the two loss values, about 1e-8 to 1e-7
+  relative (bound 1e-6); in a position it also carries the truncation error
+  h^2 |K|^2 / 6, about 1e-6 for the lattice's largest |K| (bound 1e-5).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import forward_model as fm
+from oracle.quality import rel_l2
+from paper_1510_01078_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+# the benchmark's window setting
+TUNED = dict(kernel="kaiser_bessel", sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c5():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_01078_amd import Plan
+    p = inputs.config_problem(4)
+    _say(f"[gpu] differentiable workload: M={p.m}, Nt={p.nt}, grid {p.shape}")
+    plans = {prec: Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, precision=prec, **TUNED)
+             for prec in ("fp32", "fp64")}
+    f0 = inputs.voxelise_balls(p.balls, *p.shape, *p.extent)
+    yield p, plans, f0
+    for pl in plans.values():
+        pl.close()
+
+
+def _t(a, pl):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(pl.device, pl.dtype)
+
+
+def _grid(p):
+    Nx, Ny, Nz = p.shape
+    X, Y, Z = p.extent
+    return ((np.arange(Nx) - Nx / 2) * X / Nx, (np.arange(Ny) - Ny / 2) * Y / Ny, np.arange(Nz) * Z / Nz)
+
+
+def test_plane_wave_all_outputs(c5):
+    p, plans, _ = c5
+    pl = plans["fp32"]
+    X, Y, Z = p.extent
+    x, y, z = _grid(p)
+    t = np.arange(p.nt) * p.dt
+    worst = 0.0
+    for (j0, k0, l0, phi) in [(23, -40, 17, 0.3), (-70, 61, 5, 1.1), (3, 0, 88, -0.4)]:
+        kx, ky, kz = 2 * np.pi * j0 / X, 2 * np.pi * k0 / Y, 2 * np.pi * l0 / Z
+        f = np.cos(kx * x[:, None, None] + ky * y[None, :, None] + kz * z[None, None, :] + phi)
+        ft = _t(f, pl)
+        kabs = np.sqrt(kx * kx + ky * ky + kz * kz)
+        ph = kx * p.xy[:, 0] + ky * p.xy[:, 1] + phi
+        ct = np.cos(p.c * kabs * t)[None, :]
+        g = pl.forward(ft).cpu().numpy().astype(np.float64)
+        e = rel_l2(g, np.cos(ph)[:, None] * ct)
+        for axis, kk in ((0, kx), (1, ky)):
+            if kk == 0.0:
+                continue
+            gd = pl.forward_dxy(ft, axis).cpu().numpy().astype(np.float64)
+            e = max(e, rel_l2(gd, -kk * np.sin(ph)[:, None] * ct))
+        _say(f"[gpu] plane wave ({j0},{k0},{l0}) at 192^3, all {p.m} x {p.nt} outputs and derivatives: {e:.3e}")
+        worst = max(worst, e)
+    assert worst <= 1e-5
+
+
+def test_forward_sampled_vs_oracle(c5):
+    p, plans, f0 = c5
+    g = plans["fp32"].forward(_t(f0, plans["fp32"])).cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(41)
+    ms = np.sort(rng.choice(p.m, 12, replace=False))
+    ns = np.sort(rng.choice(np.arange(100, p.nt), 16, replace=False))  # after the first arrivals
+    ref = fm.forward(f0, p.xy[ms], p.nt, p.dt, p.c, p.extent, n_index=ns)
+    e = rel_l2(g[np.ix_(ms, ns)], ref)
+    _say(f"[gpu] forward model of the phantom vs oracle on {len(ms)} sensors x {len(ns)} samples: {e:.3e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_adjointness_full_size(c5, precision, tol):
+    """The GPU kernels of A are the exact transposes of those of A*: in FP64
+    <Af, g> = <f, A*g> to rounding (1e-12); in FP32 each of the two results
+    carries its own rounding of about 1e-6, so the bound is 1e-5."""
+    p, plans, f0 = c5
+    pl = plans[precision]
+    rng = np.random.default_rng(42)
+    f = _t(rng.standard_normal(p.shape), pl)
+    g = _t(rng.standard_normal((p.m, p.nt)), pl)
+    lhs = float(torch.dot(pl.forward(f).double().reshape(-1), g.double().reshape(-1)))
+    rhs = float(torch.dot(f.double().reshape(-1), pl.adjoint(g).double().reshape(-1)))
+    e = abs(lhs - rhs) / abs(rhs)
+    _say(f"[gpu] <Af, g> vs <f, A*g> at 192^3 ({precision}): {e:.3e}")
+    assert e <= tol
+
+
+def test_gradients_all_sensors(c5):
+    from paper_1510_01078_amd.autograd import forward_model
+    p, plans, f0 = c5
+    rng = np.random.default_rng(43)
+    ns = np.sort(rng.choice(np.arange(100, p.nt), 24, replace=False))
+    w = np.zeros((p.m, p.nt))
+    w[:, ns] = rng.standard_normal((p.m, len(ns)))
+    grads = {}
+    for prec, pl in plans.items():
+        f = _t(f0, pl).requires_grad_(True)
+        xy = torch.from_numpy(p.xy.copy()).requires_grad_(True)
+        loss = (forward_model(f, xy, pl) * _t(w, pl)).sum()
+        gf, gxy = torch.autograd.grad(loss, (f, xy))
+        grads[prec] = (gf.double().cpu().numpy(), gxy.numpy())
+    gf32, gxy32 = grads["fp32"]
+    gf64, gxy64 = grads["fp64"]
+    assert gxy32.shape == (p.m, 2) and np.all(np.isfinite(gxy32))
+    sub = np.sort(rng.choice(p.m, 10, replace=False))
+    ax = fm.forward(f0, p.xy[sub], p.nt, p.dt, p.c, p.extent, deriv="x", n_index=ns)
+    ay = fm.forward(f0, p.xy[sub], p.nt, p.dt, p.c, p.extent, deriv="y", n_index=ns)
+    ws = w[np.ix_(sub, ns)]
+    g_or = np.stack([(ws * ax).sum(1), (ws * ay).sum(1)], 1)
+    e_or = rel_l2(gxy32[sub], g_or)
+    e_or64 = rel_l2(gxy64[sub], g_or)
+    e_xy = rel_l2(gxy32, gxy64)
+    e_f = rel_l2(gf32, gf64)
+    _say(f"[gpu] position gradients of all {p.m} sensors: FP32 vs oracle on {len(sub)} sensors {e_or:.3e} "
+         f"(FP64 form {e_or64:.3e}); FP32 vs FP64 on every sensor {e_xy:.3e}; image gradient FP32 vs FP64 {e_f:.3e}")
+    assert e_or <= 1e-5 and e_xy <= 1e-5 and e_f <= 1e-5
+
+
+def test_landweber_ten_iterations(c5):
+    from paper_1510_01078_amd.iterative import landweber, operator_norm_sq
+    p, plans, _ = c5
+    x0 = np.random.default_rng(44).standard_normal(p.shape)
+    out = {}
+    tau = None
+    for prec in ("fp32", "fp64"):
+        pl = plans[prec]
+        g = _t(p.g, pl)
+        if tau is None:
+            tau = 1.0 / operator_norm_sq(pl, _t(x0, pl), 20)
+            lam64 = operator_norm_sq(plans["fp64"], _t(x0, plans["fp64"]), 20)
+            _say(f"[gpu] ||A||^2 from 20 power steps: FP32 {1.0 / tau:.6e}, FP64 {lam64:.6e}")
+            assert abs(1.0 / tau - lam64) <= 1e-4 * lam64
+        f, res, _ = landweber(pl, g, iters=10, tau=tau)
+        out[prec] = (f.double().cpu().numpy(), res)
+    (f32, r32), (f64, r64) = out["fp32"], out["fp64"]
+    e = rel_l2(f32, f64)
+    _say(f"[gpu] Landweber x10 at 192^3: residual {r32[0]:.4e} -> {r32[-1]:.4e} (FP64 {r64[-1]:.4e}); "
+         f"FP32 vs FP64 iterate {e:.3e}")
+    assert all(r32[i + 1] <= r32[i] * (1 + 1e-6) for i in range(10))
+    assert r32[-1] < r32[0]
+    assert e <= 1e-4
+
+
+def test_subproblem_central_differences():
+    """16^3 grid, 8 x 8 warped sensors on the differentiable workload's plane,
+    64 samples, FP64: autograd gradients of L = <w, A f> against central
+    differences with h = 1e-6."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1510_01078_amd import Plan
+    from paper_1510_01078_amd.autograd import forward_model
+    side, nt, dt, c = 20e-3, 64, 25e-9, inputs.C_SOUND
+    xy, h = inputs.warped_sensors(8, side)
+    shape, extent = (16, 16, 16), (side, side, side)
+    kw = dict(kernel="kaiser_bessel", sigma_xy=2.0, width_xy=12, sigma_t=2.0, width_t=12)
+    rng = np.random.default_rng(45)
+    f0 = rng.standard_normal(shape)
+    w = rng.standard_normal((len(xy), nt))
+    pl = Plan(xy, nt, dt, c, shape, extent, sensor_h=h, precision="fp64", **kw)
+    f = _t(f0, pl).requires_grad_(True)
+    xyt = torch.from_numpy(xy.copy()).requires_grad_(True)
+    wt = _t(w, pl)
+    loss = (forward_model(f, xyt, pl) * wt).sum()
+    gf, gxy = torch.autograd.grad(loss, (f, xyt))
+    gf = gf.cpu().numpy()
+    gxy = gxy.numpy()
+    step = 1e-6
+
+    def L_image(fv):
+        return float((pl.forward(_t(fv, pl)).cpu().numpy() * w).sum())
+
+    vox = [(0, 0, 0), (3, 9, 4), (15, 7, 12), (8, 8, 8)]
+    fd_f = []
+    for v in vox:
+        e = np.zeros(shape)
+        e[v] = step
+        fd_f.append((L_image(f0 + e) - L_image(f0 - e)) / (2 * step))
+    pl.close()
+    sens = [0, 9, 27, 36, 63]
+    fd_xy = np.zeros((len(sens), 2))
+    for i, m in enumerate(sens):
+        for a in range(2):
+            vals = []
+            for sgn in (1, -1):
+                q = xy.copy()
+                q[m, a] += sgn * step
+                plq = Plan(q, nt, dt, c, shape, extent, sensor_h=h, precision="fp64", **kw)
+                vals.append(float((plq.forward(_t(f0, plq)).cpu().numpy() * w).sum()))
+                plq.close()
+            fd_xy[i, a] = (vals[0] - vals[1]) / (2 * step)
+    e_f = rel_l2(np.array([gf[v] for v in vox]), np.array(fd_f))
+    e_xy = rel_l2(gxy[sens], fd_xy)
+    _say(f"[gpu] 16^3 / 8x8 / 64 samples, FP64: image gradient vs central differences {e_f:.3e}, "
+         f"position gradient {e_xy:.3e}")
+    assert e_f <= 1e-6 and e_xy <= 1e-5

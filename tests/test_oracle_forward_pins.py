@@ -155,3 +155,18 @@ def test_power_iteration_and_landweber():
         acc += term
         term = N @ term
     assert np.abs(f.ravel() - acc).max() <= 1e-10 * np.abs(acc).max()
+
+
+def test_sampled_times_equal_full_columns():
+    """forward(..., n_index=...) returns exactly the selected columns of the
+    full result (each output is its own sum), with and without the position
+    derivative."""
+    rng = np.random.default_rng(19)
+    xy = _sensors(rng, 7, EXT)
+    f = rng.standard_normal(SHAPE)
+    idx = np.array([0, 3, 17, 49, 22])
+    for deriv in (None, "x", "y"):
+        full = fm.forward(f, xy, NT, DT, C, EXT, deriv=deriv)
+        part = fm.forward(f, xy, NT, DT, C, EXT, deriv=deriv, n_index=idx)
+        assert part.shape == (7, len(idx))
+        assert np.allclose(part, full[:, idx], rtol=0, atol=1e-13 * np.abs(full).max())
