@@ -31,7 +31,7 @@ bool radix_plan(int n, patk::FftRaw& f) {
   f.n = n;
   f.npass = 0;
   int radix[24], np = 0, r = n;
-  for (int R : {8, 4, 2, 5, 3})
+  for (int R : {8, 6, 4, 2, 5, 3})  // radix 6 after the 8s: 384 = 8 8 6, 288 = 8 6 6 (one pass fewer)
     while (r % R == 0 && np < 24) {
       radix[np++] = R;
       r /= R;

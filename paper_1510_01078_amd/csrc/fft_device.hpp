@@ -195,6 +195,29 @@ struct Dft<T, 5, INV> {
   }
 };
 
+// Radix 6 as two length-3 DFTs of the even and odd inputs, combined with the
+// sixth roots of unity: X_k = E_(k mod 3) + w6^k O_(k mod 3), w6^(k+3) = -w6^k.
+template <typename T, bool INV>
+struct Dft<T, 6, INV> {
+  __device__ __forceinline__ static void run(cx<T>* a) {
+    const T s = INV ? T(1) : T(-1);
+    const T h = T(0.86602540378443864676372317075294);  // sin(pi/3)
+    cx<T> e[3] = {a[0], a[2], a[4]};
+    cx<T> o[3] = {a[1], a[3], a[5]};
+    Dft<T, 3, INV>::run(e);
+    Dft<T, 3, INV>::run(o);
+    // w6 = 1/2 + s i h, w6^2 = -1/2 + s i h
+    const cx<T> o1 = cx<T>{T(0.5) * o[1].x - s * h * o[1].y, T(0.5) * o[1].y + s * h * o[1].x};
+    const cx<T> o2 = cx<T>{T(-0.5) * o[2].x - s * h * o[2].y, T(-0.5) * o[2].y + s * h * o[2].x};
+    a[0] = e[0] + o[0];
+    a[3] = e[0] - o[0];
+    a[1] = e[1] + o1;
+    a[4] = e[1] - o1;
+    a[2] = e[2] + o2;
+    a[5] = e[2] - o2;
+  }
+};
+
 // Ordering between the read and write phases of a pass: a work-group barrier,
 // or (when one wave owns the sequences) wave-local ordering of its LDS traffic.
 template <bool WAVE>
@@ -270,6 +293,7 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int bat
       case 4: stockham_pass<T, 4, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
       case 2: stockham_pass<T, 2, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
       case 3: stockham_pass<T, 3, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 6: stockham_pass<T, 6, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
       default: stockham_pass<T, 5, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
     }
   }
@@ -277,7 +301,7 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int bat
 
 // ---------------------------------------------------------------------------
 // Compile-time form for one length N: the same passes (radices taken greedily
-// in the order 8, 4, 2, 5, 3, as the host planner does), twiddle reads and
+// in the order 8, 6, 4, 2, 5, 3, as the host planner does), twiddle reads and
 // butterflies as fft_lds with the host plan for N (the compiler may fuse
 // multiplies and adds differently in the two forms, so results agree to
 // rounding, and bit for bit where it does not); with N, the radix, p and the
@@ -295,9 +319,9 @@ struct CtPlan {
 
 __host__ __device__ constexpr CtPlan ct_plan(int n) {
   CtPlan c{0, {}};
-  const int rs[5] = {8, 4, 2, 5, 3};
+  const int rs[6] = {8, 6, 4, 2, 5, 3};
   int m = n;
-  for (int q = 0; q < 5; ++q)
+  for (int q = 0; q < 6; ++q)
     while (m % rs[q] == 0 && c.np < 16) {
       c.r[c.np++] = rs[q];
       m /= rs[q];
