@@ -97,6 +97,55 @@ __device__ __forceinline__ void staged_copy(int count, int tid, int nthr, Load l
   }
 }
 
+// The same for the compile-time FFT kernels, whose geometry is known: a block
+// of nrows <= ROWS rows of N elements, thread t taking elements t, t + NT, ...
+// of every row, so no index needs a division (ld(r, c), st(r, c, v)).
+template <int ROWS, int N, int NT, typename Load, typename Store>
+__device__ __forceinline__ void staged_rows(int nrows, int tid, Load ld, Store st) {
+  constexpr int CPR = (N + NT - 1) / NT;
+  static_assert(ROWS * CPR <= 16, "at most 16 staged values per thread");
+  using V = decltype(ld(0, 0));
+  V tmp[ROWS][CPR];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+    for (int k = 0; k < CPR; ++k) {
+      const int c = tid + k * NT;
+      if (r < nrows && (N % NT == 0 || c < N)) tmp[r][k] = ld(r, c);
+    }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+#pragma unroll
+    for (int k = 0; k < CPR; ++k) {
+      const int c = tid + k * NT;
+      if (r < nrows && (N % NT == 0 || c < N)) st(r, c, tmp[r][k]);
+    }
+}
+
+// Columns of a ROWS-row block written out column by column (element (j, r)
+// of column j < ncols, row r < nrows): thread t takes row t % ROWS of columns
+// t / ROWS + u * (NT / ROWS), u = 0, 1, ... (at most U of them), so
+// neighbouring threads write neighbouring rows of one column and the column
+// index steps by a constant (ld(j, r, u), st(j, r, u, v)).
+template <int ROWS, int NT, int U, typename Load, typename Store>
+__device__ __forceinline__ void staged_cols(int ncols, int nrows, int tid, Load ld, Store st) {
+  static_assert(NT % ROWS == 0, "rows must divide the thread count");
+  constexpr int CPI = NT / ROWS;
+  using V = decltype(ld(0, 0, 0));
+  const int r = tid % ROWS, j0 = tid / ROWS;
+  V tmp[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = j0 + u * CPI;
+    if (j < ncols && r < nrows) tmp[u] = ld(j, r, u);
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int j = j0 + u * CPI;
+    if (j < ncols && r < nrows) st(j, r, u, tmp[u]);
+  }
+}
+
 // LDS slot of element a of a sequence: one pad slot after every
 // 2^kLdsPadShift elements, so the stride-R stores of the first radix-8
 // passes hit distinct banks. Runs of 16 measured fastest on MI355X: a pad

@@ -18,41 +18,59 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int n_x = fd.n;
+  const int n_x = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_x);
   const int b = b_begin + by;
   const int py0 = bx * rows;
   const int nr = min(rows, n_y - py0);
   const cx<T>* src = U + (size_t(b - b_begin) * n_y + py0) * n_x;
-  const FastDiv div_nx(n_x), div_nr(nr);
-  staged_copy<kFftMaxV>(
-      nr * n_x, tid, nthr, [&](int q) { return src[q]; },
-      [&](int q, cx<T> v) {
-        const int r = div_nx(q);
-        buf[r * bstride + lpos(q - r * n_x)] = v;
-      });
-  // the twiddles go to LDS behind the rows (every pass reads them)
-  cx<T>* twl = buf + rows * bstride;
-  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
-  __syncthreads();
-  if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nr, twl, tid);
-  else
-    fft_group<T, false>(buf, lds_twiddles(fd, twl), nr, bstride, tid, nthr, wm);
-  __syncthreads();
   cx<T>* dst = V + size_t(b) * Nx * n_y + py0;
-  staged_copy<kFftMaxV>(
-      nr * Nx, tid, nthr,
-      [&](int q) {
-        const int jj = div_nr(q);
-        const int r = q - jj * nr;
-        const int j = jj < Nx / 2 ? jj : jj - Nx;
-        return buf[r * bstride + lpos(j < 0 ? j + n_x : j)];
-      },
-      [&](int q, cx<T> v) {
-        const int jj = div_nr(q);
-        dst[size_t(jj) * n_y + (q - jj * nr)] = v;
-      });
+  // output mode jj of the Nx kept, centred, at its slot of the n_x transform
+  auto slot = [&](int jj) {
+    const int j = jj < Nx / 2 ? jj : jj - Nx;
+    return lpos(j < 0 ? j + n_x : j);
+  };
+  cx<T>* twl = buf + rows * bstride;
+  if constexpr (NCT > 0) {
+    // compile-time geometry (rows = ROWS, 256 threads): no index divisions
+    constexpr int ROWS = ct_maxb(NCT, kFftCap), BS = lseq(NCT);
+    staged_rows<ROWS, NCT, kFftThreads>(
+        nr, tid, [&](int r, int c) { return src[r * NCT + c]; },
+        [&](int r, int c, cx<T> v) { buf[r * BS + lpos(c)] = v; });
+    for (int t = tid; t < NCT; t += kFftThreads) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_ct<T, NCT, kFftThreads, ROWS, false>(buf, nr, twl, tid);
+    __syncthreads();
+    // V[b][jj][py0 + r]: neighbouring threads write neighbouring rows
+    cx<T>* d0 = dst + size_t(tid / ROWS) * n_y + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * n_y;
+    staged_cols<ROWS, kFftThreads, (NCT * ROWS + kFftThreads - 1) / kFftThreads>(  // Nx < n_x = NCT
+        Nx, nr, tid, [&](int jj, int r, int) { return buf[r * BS + slot(jj)]; },
+        [&](int, int, int u, cx<T> v) { d0[u * step] = v; });
+  } else {
+    const FastDiv div_nx(n_x), div_nr(nr);
+    staged_copy<kFftMaxV>(
+        nr * n_x, tid, nthr, [&](int q) { return src[q]; },
+        [&](int q, cx<T> v) {
+          const int r = div_nx(q);
+          buf[r * bstride + lpos(q - r * n_x)] = v;
+        });
+    // the twiddles go to LDS behind the rows (every pass reads them)
+    for (int t = tid; t < fd.n; t += nthr) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_group<T, false>(buf, lds_twiddles(fd, twl), nr, bstride, tid, nthr, wm);
+    __syncthreads();
+    staged_copy<kFftMaxV>(
+        nr * Nx, tid, nthr,
+        [&](int q) {
+          const int jj = div_nr(q);
+          return buf[(q - jj * nr) * bstride + slot(jj)];
+        },
+        [&](int q, cx<T> v) {
+          const int jj = div_nr(q);
+          dst[size_t(jj) * n_y + (q - jj * nr)] = v;
+        });
+  }
 }
 
 template <typename T, int NCT>
@@ -72,7 +90,9 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
   if (size_t(rows) * p.n_x > size_t(kFftMaxV) * cfg.threads || size_t(rows) * p.Nx > size_t(kFftMaxV) * cfg.threads ||
       b_begin < 0 || b_end > p.nb || b_begin >= b_end)
     return hipErrorInvalidValue;
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, int nct) {
+    // the compile-time kernels take their geometry from the length
+    if (nct > 0 && (rows != ct_maxb(nct, kFftCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
     dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
@@ -80,7 +100,7 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
                        b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
     return hipGetLastError();
   };
-  return ct_pick(CtLateral{}, p.n_x, [&](auto c) { return go(&k_fft_x<T, decltype(c)::value>); });
+  return ct_pick(CtLateral{}, p.n_x, [&](auto c) { return go(&k_fft_x<T, decltype(c)::value>, decltype(c)::value); });
 }
 
 // ---------------------------------------------------------------------------
@@ -98,47 +118,73 @@ __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int n_y = fd.n;
+  const int n_y = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_y);
   const int jj = by;
   const int b0 = bx * bins;
   const int nbc = min(bins, nb - b0);
   if (jrange && (b0 + nbc - 1 < jrange[2 * jj] || b0 > jrange[2 * jj + 1])) return;
-  const FastDiv div_ny(n_y), div_nbc(nbc);
-  staged_copy<kFftMaxV>(
-      nbc * n_y, tid, nthr,
-      [&](int q) {
-        const int bi = div_ny(q);
-        return V[(size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y)];
-      },
-      [&](int q, cx<T> v) {
-        const int bi = div_ny(q);
-        buf[bi * bstride + lpos(q - bi * n_y)] = v;
-      });
-  cx<T>* twl = buf + bins * bstride;
-  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
-  __syncthreads();
-  if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), false>(buf, nbc, twl, tid);
-  else
-    fft_group<T, false>(buf, lds_twiddles(fd, twl), nbc, bstride, tid, nthr, wm);
-  __syncthreads();
+  const cx<T>* src = V + (size_t(b0) * Nx + jj) * n_y;  // bin b0 + bi at src + bi * Nx * n_y
+  const size_t bin_stride = size_t(Nx) * n_y;
   const T cxj = dcx[jj];
   cx<T>* dst = Gh + size_t(jj) * Ny * nb + b0;
-  staged_copy<kFftMaxV>(
-      nbc * Ny, tid, nthr,
-      [&](int q) {
-        const int kk = div_nbc(q);
-        const int bi = q - kk * nbc;
-        const int k = kk < Ny / 2 ? kk : kk - Ny;
-        const T sc = cxj * dcy[kk];
-        const cx<T> v = buf[bi * bstride + lpos(k < 0 ? k + n_y : k)];
-        return cx<T>{v.x * sc, v.y * sc};
-      },
-      [&](int q, cx<T> v) {
-        const int kk = div_nbc(q);
-        dst[size_t(kk) * nb + (q - kk * nbc)] = v;
-      });
+  // output mode kk of the Ny kept, centred, at its slot of the n_y transform
+  auto slot = [&](int kk) {
+    const int k = kk < Ny / 2 ? kk : kk - Ny;
+    return lpos(k < 0 ? k + n_y : k);
+  };
+  cx<T>* twl = buf + bins * bstride;
+  if constexpr (NCT > 0) {
+    // compile-time geometry (bins = ROWS, 256 threads): no index divisions
+    constexpr int ROWS = ct_maxb(NCT, kFftCap), BS = lseq(NCT);
+    staged_rows<ROWS, NCT, kFftThreads>(
+        nbc, tid, [&](int r, int c) { return src[r * bin_stride + c]; },
+        [&](int r, int c, cx<T> v) { buf[r * BS + lpos(c)] = v; });
+    for (int t = tid; t < NCT; t += kFftThreads) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_ct<T, NCT, kFftThreads, ROWS, false>(buf, nbc, twl, tid);
+    __syncthreads();
+    // Gh[jj][kk][b0 + bi]: neighbouring threads write neighbouring bins
+    cx<T>* d0 = dst + size_t(tid / ROWS) * nb + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * nb;
+    staged_cols<ROWS, kFftThreads, (NCT * ROWS + kFftThreads - 1) / kFftThreads>(  // Ny < n_y = NCT
+        Ny, nbc, tid,
+        [&](int kk, int bi, int) {
+          const T sc = cxj * dcy[kk];
+          const cx<T> v = buf[bi * BS + slot(kk)];
+          return cx<T>{v.x * sc, v.y * sc};
+        },
+        [&](int, int, int u, cx<T> v) { d0[u * step] = v; });
+  } else {
+    const FastDiv div_ny(n_y), div_nbc(nbc);
+    staged_copy<kFftMaxV>(
+        nbc * n_y, tid, nthr,
+        [&](int q) {
+          const int bi = div_ny(q);
+          return src[bi * bin_stride + (q - bi * n_y)];
+        },
+        [&](int q, cx<T> v) {
+          const int bi = div_ny(q);
+          buf[bi * bstride + lpos(q - bi * n_y)] = v;
+        });
+    for (int t = tid; t < fd.n; t += nthr) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_group<T, false>(buf, lds_twiddles(fd, twl), nbc, bstride, tid, nthr, wm);
+    __syncthreads();
+    staged_copy<kFftMaxV>(
+        nbc * Ny, tid, nthr,
+        [&](int q) {
+          const int kk = div_nbc(q);
+          const int bi = q - kk * nbc;
+          const T sc = cxj * dcy[kk];
+          const cx<T> v = buf[bi * bstride + slot(kk)];
+          return cx<T>{v.x * sc, v.y * sc};
+        },
+        [&](int q, cx<T> v) {
+          const int kk = div_nbc(q);
+          dst[size_t(kk) * nb + (q - kk * nbc)] = v;
+        });
+  }
 }
 
 template <typename T, int NCT>
@@ -159,7 +205,9 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
   const size_t lds = (size_t(bins) * lseq(p.n_y) + p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, int nct) {
+    // the compile-time kernels take their geometry from the length
+    if (nct > 0 && (bins != ct_maxb(nct, kFftCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
     dim3 grid((p.nb + bins - 1) / bins, p.Nx);
@@ -168,7 +216,7 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
                        static_cast<cx<T>*>(Gh), cfg.wave, p.jrange);
     return hipGetLastError();
   };
-  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y<T, decltype(c)::value>); });
+  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y<T, decltype(c)::value>, decltype(c)::value); });
 }
 
 // ---------------------------------------------------------------------------
@@ -240,7 +288,9 @@ hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t
   const size_t lds = (size_t(bins) * lseq(p.n_y) + p.n_y) * sizeof(cx<T>);
   if (size_t(bins) * p.n_y > size_t(kFftMaxV) * cfg.threads || size_t(bins) * p.Ny > size_t(kFftMaxV) * cfg.threads)
     return hipErrorInvalidValue;
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, int nct) {
+    // the compile-time kernels take their geometry from the length
+    if (nct > 0 && (bins != ct_maxb(nct, kFftCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
     dim3 grid((p.nb + bins - 1) / bins, p.Nx);
@@ -249,7 +299,7 @@ hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t
                        static_cast<cx<T>*>(V), p.jrange);
     return hipGetLastError();
   };
-  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y_t<T, decltype(c)::value>); });
+  return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y_t<T, decltype(c)::value>, decltype(c)::value); });
 }
 
 // V'[b][j][py] -> U'[b - b_begin][py][px] = sum_j V'[b][j][py] e^{+2 pi i j px/n_x}
