@@ -214,6 +214,9 @@ __device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int 
   for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   const FastDiv div_nl(nl);
+  // (one loop form for every length: the batched reconstruction runs this
+  // loop too, and the same code keeps the two paths' values bit for bit equal)
+  constexpr int ROWS = NCT > 0 ? ct_maxb(NCT, kInvCap) : 1;
   for (int q = tid; q < nl * Nx; q += nthr) {
     const int jj = div_nl(q);
     const int li = q - jj * nl;
@@ -223,20 +226,30 @@ __device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int 
   }
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, nl, twl, tid);
+    fft_ct<T, NCT, kFftThreads, ROWS, true>(buf, nl, twl, tid);
   else
     fft_group<T, true>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
   __syncthreads();
-  staged_copy<kFftMaxV>(
-      nl * Nx, tid, nthr,
-      [&](int q) {
-        const int jj = div_nl(q);
-        return buf[(q - jj * nl) * bstride + lpos(jj)];
-      },
-      [&](int q, cx<T> v) {
-        const int jj = div_nl(q);
-        F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)] = v;
-      });
+  cx<T>* base = F + size_t(kk) * Lh + l0;  // x mode jj, z mode l0 + li at base[jj * Ny * Lh + li]
+  const size_t col = size_t(Ny) * Lh;
+  if constexpr (NCT > 0) {
+    cx<T>* b0 = base + size_t(tid / ROWS) * col + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * col;
+    staged_cols<ROWS, kFftThreads, NCT * ROWS / kFftThreads>(  // Nx = NCT
+        NCT, nl, tid, [&](int jj, int li, int) { return buf[li * bstride + lpos(jj)]; },
+        [&](int, int, int u, cx<T> v) { b0[u * step] = v; });
+  } else {
+    staged_copy<kFftMaxV>(
+        nl * Nx, tid, nthr,
+        [&](int q) {
+          const int jj = div_nl(q);
+          return buf[(q - jj * nl) * bstride + lpos(jj)];
+        },
+        [&](int q, cx<T> v) {
+          const int jj = div_nl(q);
+          base[jj * col + (q - jj * nl)] = v;
+        });
+  }
 }
 
 template <typename T, int MODE, int WT, int NCT>
@@ -288,6 +301,8 @@ hipError_t launch_gather_x(const DevPlan& p, const void* Gh, void* F, int mode, 
     constexpr int WT = decltype(w)::value;
     return ct_pick(CtInverse{}, p.Nx, [&](auto c) {
       constexpr int NCT = decltype(c)::value;
+      // the compile-time kernels take their geometry from the length
+      if (NCT > 0 && (lc != ct_maxb(NCT, kInvCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
       const void* kern = adj ? reinterpret_cast<const void*>(&k_gather_x<T, MODE_ADJOINT, WT, NCT>)
                              : reinterpret_cast<const void*>(&k_gather_x<T, MODE_IMAGE, WT, NCT>);
       hipError_t e = allow_lds(kern, lds);

@@ -19,40 +19,56 @@ __device__ __forceinline__ void cfft_x_body(cx<T>* __restrict__ F, int Ny, int L
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int Nx = fd.n;
+  const int Nx = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(Nx);
   const int kk = by;
   const int l0 = bx * lchunk;
   const int nl = min(lchunk, Lh - l0);
-  const FastDiv div_nl(nl);
-  staged_copy<kFftMaxV>(
-      nl * Nx, tid, nthr,
-      [&](int q) {
-        const int jj = div_nl(q);
-        return F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)];
-      },
-      [&](int q, cx<T> v) {
-        const int jj = div_nl(q);
-        buf[(q - jj * nl) * bstride + lpos(jj)] = v;
-      });
+  cx<T>* base = F + size_t(kk) * Lh + l0;  // x mode jj, z mode l0 + li at base[jj * Ny * Lh + li]
+  const size_t col = size_t(Ny) * Lh;
   cx<T>* twl = buf + lchunk * bstride;  // the twiddles go to LDS behind the rows
-  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
-  __syncthreads();
-  if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
-  else
+  if constexpr (NCT > 0) {
+    // compile-time geometry (lchunk = ROWS z modes, 256 threads): no index divisions
+    constexpr int ROWS = ct_maxb(NCT, kInvCap), BS = lseq(NCT), U = NCT * ROWS / kFftThreads;
+    cx<T>* b0 = base + size_t(tid / ROWS) * col + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * col;
+    staged_cols<ROWS, kFftThreads, U>(
+        NCT, nl, tid, [&](int, int, int u) { return b0[u * step]; },
+        [&](int jj, int li, int, cx<T> v) { buf[li * BS + lpos(jj)] = v; });
+    for (int t = tid; t < NCT; t += kFftThreads) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_ct<T, NCT, kFftThreads, ROWS, INV>(buf, nl, twl, tid);
+    __syncthreads();
+    staged_cols<ROWS, kFftThreads, U>(
+        NCT, nl, tid, [&](int jj, int li, int) { return buf[li * BS + lpos(jj)]; },
+        [&](int, int, int u, cx<T> v) { b0[u * step] = v; });
+  } else {
+    const FastDiv div_nl(nl);
+    staged_copy<kFftMaxV>(
+        nl * Nx, tid, nthr,
+        [&](int q) {
+          const int jj = div_nl(q);
+          return base[jj * col + (q - jj * nl)];
+        },
+        [&](int q, cx<T> v) {
+          const int jj = div_nl(q);
+          buf[(q - jj * nl) * bstride + lpos(jj)] = v;
+        });
+    for (int t = tid; t < fd.n; t += nthr) twl[t] = fd.tw[t];
+    __syncthreads();
     fft_group<T, INV>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
-  __syncthreads();
-  staged_copy<kFftMaxV>(
-      nl * Nx, tid, nthr,
-      [&](int q) {
-        const int jj = div_nl(q);
-        return buf[(q - jj * nl) * bstride + lpos(jj)];
-      },
-      [&](int q, cx<T> v) {
-        const int jj = div_nl(q);
-        F[(size_t(jj) * Ny + kk) * Lh + l0 + (q - jj * nl)] = v;
-      });
+    __syncthreads();
+    staged_copy<kFftMaxV>(
+        nl * Nx, tid, nthr,
+        [&](int q) {
+          const int jj = div_nl(q);
+          return buf[(q - jj * nl) * bstride + lpos(jj)];
+        },
+        [&](int q, cx<T> v) {
+          const int jj = div_nl(q);
+          base[jj * col + (q - jj * nl)] = v;
+        });
+  }
 }
 
 template <typename T, bool INV, int NCT>
@@ -69,41 +85,55 @@ __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int l
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int Ny = fd.n;
+  const int Ny = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(Ny);
   const int jj = by;
   const int l0 = bx * lchunk;
   const int nl = min(lchunk, Lh - l0);
   cx<T>* base = F + size_t(jj) * Ny * Lh + l0;
-  const FastDiv div_nl(nl);
-  staged_copy<kFftMaxV>(
-      nl * Ny, tid, nthr,
-      [&](int q) {
-        const int kk = div_nl(q);
-        return base[size_t(kk) * Lh + (q - kk * nl)];
-      },
-      [&](int q, cx<T> v) {
-        const int kk = div_nl(q);
-        buf[(q - kk * nl) * bstride + lpos(kk)] = v;
-      });
   cx<T>* twl = buf + lchunk * bstride;  // the twiddles go to LDS behind the rows
-  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
-  __syncthreads();
-  if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), INV>(buf, nl, twl, tid);
-  else
+  if constexpr (NCT > 0) {
+    // compile-time geometry (lchunk = ROWS z modes, 256 threads): no index divisions
+    constexpr int ROWS = ct_maxb(NCT, kInvCap), BS = lseq(NCT), U = NCT * ROWS / kFftThreads;
+    cx<T>* b0 = base + size_t(tid / ROWS) * Lh + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * Lh;
+    staged_cols<ROWS, kFftThreads, U>(
+        NCT, nl, tid, [&](int, int, int u) { return b0[u * step]; },
+        [&](int kk, int li, int, cx<T> v) { buf[li * BS + lpos(kk)] = v; });
+    for (int t = tid; t < NCT; t += kFftThreads) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_ct<T, NCT, kFftThreads, ROWS, INV>(buf, nl, twl, tid);
+    __syncthreads();
+    staged_cols<ROWS, kFftThreads, U>(
+        NCT, nl, tid, [&](int kk, int li, int) { return buf[li * BS + lpos(kk)]; },
+        [&](int, int, int u, cx<T> v) { b0[u * step] = v; });
+  } else {
+    const FastDiv div_nl(nl);
+    staged_copy<kFftMaxV>(
+        nl * Ny, tid, nthr,
+        [&](int q) {
+          const int kk = div_nl(q);
+          return base[size_t(kk) * Lh + (q - kk * nl)];
+        },
+        [&](int q, cx<T> v) {
+          const int kk = div_nl(q);
+          buf[(q - kk * nl) * bstride + lpos(kk)] = v;
+        });
+    for (int t = tid; t < fd.n; t += nthr) twl[t] = fd.tw[t];
+    __syncthreads();
     fft_group<T, INV>(buf, lds_twiddles(fd, twl), nl, bstride, tid, nthr, wm);
-  __syncthreads();
-  staged_copy<kFftMaxV>(
-      nl * Ny, tid, nthr,
-      [&](int q) {
-        const int kk = div_nl(q);
-        return buf[(q - kk * nl) * bstride + lpos(kk)];
-      },
-      [&](int q, cx<T> v) {
-        const int kk = div_nl(q);
-        base[size_t(kk) * Lh + (q - kk * nl)] = v;
-      });
+    __syncthreads();
+    staged_copy<kFftMaxV>(
+        nl * Ny, tid, nthr,
+        [&](int q) {
+          const int kk = div_nl(q);
+          return buf[(q - kk * nl) * bstride + lpos(kk)];
+        },
+        [&](int q, cx<T> v) {
+          const int kk = div_nl(q);
+          base[size_t(kk) * Lh + (q - kk * nl)] = v;
+        });
+  }
 }
 
 template <typename T, bool INV, int NCT>
@@ -120,7 +150,7 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int Nz = fd.n;
+  const int Nz = NCT > 0 ? NCT : fd.n;
   const int Lh = Nz / 2 + 1;
   const int bstride = lseq(Nz);
   const long long r0 = (long long)bx * rows;
@@ -129,7 +159,10 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
   // extended) transforms to x0 + i x1. The DC and Nyquist bins keep their
   // real parts only, as the real part of a single row's transform would.
   const int np = (nr + 1) / 2;
-  const FastDiv div_lh(Lh), div_nz(Nz);
+  const FastDiv fdiv_lh(Lh), fdiv_nz(Nz);
+  // compile-time lengths divide by constants (a shift for Nz)
+  auto div_lh = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT / 2 + 1)) : fdiv_lh(q); };
+  auto div_nz = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT > 0 ? NCT : 1)) : fdiv_nz(q); };
   struct Two {
     cx<T> a, c;
   };
@@ -183,12 +216,15 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int Nz = fd.n;
+  const int Nz = NCT > 0 ? NCT : fd.n;
   const int Lh = Nz / 2 + 1;
   const int bstride = lseq(Nz);
   const long long r0 = (long long)blockIdx.x * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
-  const FastDiv div_lh(Lh), div_nz(Nz);
+  const FastDiv fdiv_lh(Lh), fdiv_nz(Nz);
+  // compile-time lengths divide by constants (a shift for Nz)
+  auto div_lh = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT / 2 + 1)) : fdiv_lh(q); };
+  auto div_nz = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT > 0 ? NCT : 1)) : fdiv_nz(q); };
   staged_copy<kFftMaxV>(
       nr * Nz, tid, nthr, [&](int q) { return f[r0 * Nz + q]; },
       [&](int q, T v) {
@@ -224,7 +260,10 @@ static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_
       const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
       const size_t lds = (size_t(lc) * lseq(p.Nx) + p.Nx) * sizeof(cx<T>);
       e = ct_pick(CtInverse{}, p.Nx, [&](auto c) {
-        const void* kern = reinterpret_cast<const void*>(&k_cfft_x<T, INV, decltype(c)::value>);
+        constexpr int NCT = decltype(c)::value;
+        // the compile-time kernels take their geometry from the length
+        if (NCT > 0 && (lc != ct_maxb(NCT, kInvCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
+        const void* kern = reinterpret_cast<const void*>(&k_cfft_x<T, INV, NCT>);
         hipError_t e2 = allow_lds(kern, lds);
         if (e2 != hipSuccess) return e2;
         dim3 grid((Lh + lc - 1) / lc, p.Ny);
@@ -236,7 +275,9 @@ static hipError_t launch_xy(const DevPlan& p, cx<T>* F, bool x_first, hipStream_
       const int lc = fft_batch<T>(p.Ny, cfg.threads, cfg.cap);
       const size_t lds = (size_t(lc) * lseq(p.Ny) + p.Ny) * sizeof(cx<T>);
       e = ct_pick(CtInverse{}, p.Ny, [&](auto c) {
-        const void* kern = reinterpret_cast<const void*>(&k_cfft_y<T, INV, decltype(c)::value>);
+        constexpr int NCT = decltype(c)::value;
+        if (NCT > 0 && (lc != ct_maxb(NCT, kInvCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
+        const void* kern = reinterpret_cast<const void*>(&k_cfft_y<T, INV, NCT>);
         hipError_t e2 = allow_lds(kern, lds);
         if (e2 != hipSuccess) return e2;
         dim3 grid((Lh + lc - 1) / lc, p.Nx);
