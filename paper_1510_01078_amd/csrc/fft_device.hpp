@@ -395,13 +395,25 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
   constexpr int BS = lseq(N);
   constexpr int K = (NBF * MAXB + NT - 1) / NT;
   const int total = NBF * batch;
+  // butterfly (sequence f, index i) of iteration it: idx = tid + it*NT, with
+  // f and i stepped from the previous iteration's (no divisions after the first)
+  int fq[K], iq[K];
+  fq[0] = tid / NBF;
+  iq[0] = tid - fq[0] * NBF;
+#pragma unroll
+  for (int it = 1; it < K; ++it) {
+    constexpr int DF = NT / NBF, DI = NT % NBF;
+    const bool wrap = iq[it - 1] + DI >= NBF;
+    iq[it] = iq[it - 1] + DI - (wrap ? NBF : 0);
+    fq[it] = fq[it - 1] + DF + (wrap ? 1 : 0);
+  }
   cx<T> v[K][R];
 #pragma unroll
   for (int it = 0; it < K; ++it) {
     const int idx = tid + it * NT;
     if (idx < total) {
-      const int f = idx / NBF;
-      const int i = idx - f * NBF;
+      const int f = fq[it];
+      const int i = iq[it];
       const cx<T>* src = buf + f * BS;
       if constexpr (NBF % kLdsPadRun == 0) {
         const cx<T>* s0 = src + lpos(i);
@@ -431,8 +443,8 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
   for (int it = 0; it < K; ++it) {
     const int idx = tid + it * NT;
     if (idx < total) {
-      const int f = idx / NBF;
-      const int i = idx - f * NBF;
+      const int f = fq[it];
+      const int i = iq[it];
       cx<T>* dst = buf + f * BS;
       if constexpr (P == 1) {
         // j0 = i*R; for R = 8 the outputs r share one padded run: lpos(8i) + r

@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int n_y = fd.n;
+  const int n_y = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_y);
   const int jj = blockIdx.y;  // (an XCD-grouped order measured slower here)
   const int b0 = blockIdx.x * bins;
@@ -241,44 +241,73 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict
   // bins outside the x-mode's range hold zeros that nothing reads: skipped
   if (jrange && (b0 + nbc - 1 < jrange[2 * jj] || b0 > jrange[2 * jj + 1])) return;
   const int gap = n_y - Ny;  // zero slots k = Ny/2 .. n_y - Ny/2 - 1
-  const FastDiv div_gap(gap), div_nbc(nbc), div_ny(n_y);
-  for (int q = tid; q < nbc * gap; q += nthr) {
-    const int bi = div_gap(q);
-    buf[bi * bstride + lpos(Ny / 2 + (q - bi * gap))] = cx<T>{T(0), T(0)};
-  }
   const T cxj = dcx[jj];
   const cx<T>* src = Gh + size_t(jj) * Ny * nb + b0;
-  staged_copy<kFftMaxV>(
-      nbc * Ny, tid, nthr,
-      [&](int q) {
-        const int kk = div_nbc(q);
-        const T sc = cxj * dcy[kk];
-        const cx<T> v = src[size_t(kk) * nb + (q - kk * nbc)];
-        return cx<T>{v.x * sc, v.y * sc};
-      },
-      [&](int q, cx<T> v) {
-        const int kk = div_nbc(q);
-        const int k = kk < Ny / 2 ? kk : kk - Ny;
-        buf[(q - kk * nbc) * bstride + lpos(k < 0 ? k + n_y : k)] = v;
-      });
+  auto slot = [&](int kk) {
+    const int k = kk < Ny / 2 ? kk : kk - Ny;
+    return lpos(k < 0 ? k + n_y : k);
+  };
   cx<T>* twl = buf + bins * bstride;
-  for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
-  __syncthreads();
-  if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kFftCap), true>(buf, nbc, twl, tid);
-  else
+  if constexpr (NCT > 0) {
+    // compile-time geometry (bins = ROWS, 256 threads): no index divisions
+    constexpr int ROWS = ct_maxb(NCT, kFftCap), BS = lseq(NCT);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r)
+      if (r < nbc)
+        for (int c = tid; c < gap; c += kFftThreads) buf[r * BS + lpos(Ny / 2 + c)] = cx<T>{T(0), T(0)};
+    const cx<T>* s0 = src + size_t(tid / ROWS) * nb + tid % ROWS;
+    const size_t step = size_t(kFftThreads / ROWS) * nb;
+    staged_cols<ROWS, kFftThreads, (NCT * ROWS + kFftThreads - 1) / kFftThreads>(  // Ny < n_y = NCT
+        Ny, nbc, tid,
+        [&](int kk, int, int u) {
+          const T sc = cxj * dcy[kk];
+          const cx<T> v = s0[u * step];
+          return cx<T>{v.x * sc, v.y * sc};
+        },
+        [&](int kk, int bi, int, cx<T> v) { buf[bi * BS + slot(kk)] = v; });
+    for (int t = tid; t < NCT; t += kFftThreads) twl[t] = fd.tw[t];
+    __syncthreads();
+    fft_ct<T, NCT, kFftThreads, ROWS, true>(buf, nbc, twl, tid);
+    __syncthreads();
+    cx<T>* v0 = V + (size_t(b0) * Nx + jj) * NCT;  // bin b0 + r at v0 + r * Nx * NCT
+    const size_t bin_stride = size_t(Nx) * NCT;
+    staged_rows<ROWS, NCT, kFftThreads>(
+        nbc, tid, [&](int r, int c) { return buf[r * BS + lpos(c)]; },
+        // non-temporal: streams out once (measured faster for the fused reader)
+        [&](int r, int c, cx<T> v) { nt_store(v0 + r * bin_stride + c, v); });
+  } else {
+    const FastDiv div_gap(gap), div_nbc(nbc), div_ny(n_y);
+    for (int q = tid; q < nbc * gap; q += nthr) {
+      const int bi = div_gap(q);
+      buf[bi * bstride + lpos(Ny / 2 + (q - bi * gap))] = cx<T>{T(0), T(0)};
+    }
+    staged_copy<kFftMaxV>(
+        nbc * Ny, tid, nthr,
+        [&](int q) {
+          const int kk = div_nbc(q);
+          const T sc = cxj * dcy[kk];
+          const cx<T> v = src[size_t(kk) * nb + (q - kk * nbc)];
+          return cx<T>{v.x * sc, v.y * sc};
+        },
+        [&](int q, cx<T> v) {
+          const int kk = div_nbc(q);
+          buf[(q - kk * nbc) * bstride + slot(kk)] = v;
+        });
+    for (int t = tid; t < fd.n; t += nthr) twl[t] = fd.tw[t];
+    __syncthreads();
     fft_lds<T, kFftMaxV, true, false>(buf, lds_twiddles(fd, twl), nbc, bstride, tid, nthr);
-  __syncthreads();
-  staged_copy<kFftMaxV>(
-      nbc * n_y, tid, nthr,
-      [&](int q) {
-        const int bi = div_ny(q);
-        return buf[bi * bstride + lpos(q - bi * n_y)];
-      },
-      [&](int q, cx<T> v) {  // non-temporal: streams out once (measured faster for the fused reader)
-        const int bi = div_ny(q);
-        nt_store(V + (size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y), v);
-      });
+    __syncthreads();
+    staged_copy<kFftMaxV>(
+        nbc * n_y, tid, nthr,
+        [&](int q) {
+          const int bi = div_ny(q);
+          return buf[bi * bstride + lpos(q - bi * n_y)];
+        },
+        [&](int q, cx<T> v) {  // non-temporal: streams out once (measured faster for the fused reader)
+          const int bi = div_ny(q);
+          nt_store(V + (size_t(b0 + bi) * Nx + jj) * n_y + (q - bi * n_y), v);
+        });
+  }
 }
 
 template <typename T>
