@@ -133,6 +133,13 @@ hipError_t launch_interp(const DevPlan& p, const void* U, void* Gt, int b_begin,
 // agree to rounding.
 // ---------------------------------------------------------------------------
 constexpr int kFusedThreads = 512;  // per home-tile row of the strip
+constexpr int kFusedBins = 8;       // most bins per work-group
+// sensors per thread whose bins are held in registers: as many as fit the
+// register budget without spills (FP32 footprints up to 8 or 12 points)
+template <typename T, int W>
+__host__ __device__ constexpr int fused_held() {
+  return sizeof(T) == 4 ? (W <= 8 ? 2 : (W <= 12 ? 1 : 0)) : 0;
+}
 
 template <int W, int FS>
 __host__ __device__ constexpr int fused_rows() { return FS * kSpreadTile + W - 1; }
@@ -208,6 +215,8 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
   const size_t plane = size_t(Nx) * n_y;
   const int total = R * Nx;
   // grid row of each strip row (periodic in y; short axes wrap more than once)
+  constexpr int HELD = fused_held<T, W>();
+  cx<T> held[HELD > 0 ? HELD : 1][kFusedBins];
   __shared__ int s_row[R];
   for (int r = tid; r < R; r += nthr) s_row[r] = (py0 + r) % n_y;
   __syncthreads();  // every wave reads the table in the first bin's staging loop
@@ -253,12 +262,41 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
         fft_lds<T, MAXV, true, true>(buf + r * bstride, fd, 1, bstride, lane, 64);
     }
     __syncthreads();
-    for (int q = q0 + tid; q < q1; q += nthr) {
+    // the first HELD sensors of every thread keep their values in
+    // registers until the group's last bin (shifted one place per bin), so
+    // each sensor's run of bins goes out in one burst instead of as single
+    // 8-byte writes to lines the L2 has evicted in between
+#pragma unroll
+    for (int k = 0; k < HELD; ++k) {
+      const int q = q0 + tid + k * nthr;
+      cx<T> val{T(0), T(0)};
+      if (q < q1) {
+        FusedSensor<T, W> f;
+        fused_sensor_load<T, W>(f, home_sens[q], py0, n_x, sbx, sby, swx, swy);
+        val = fused_sensor_sum<T, W>(f, buf, bstride);
+      }
+#pragma unroll
+      for (int j = 0; j + 1 < kFusedBins; ++j) held[k][j] = held[k][j + 1];
+      held[k][kFusedBins - 1] = val;
+    }
+    for (int q = q0 + tid + HELD * nthr; q < q1; q += nthr) {
       FusedSensor<T, W> f;
       fused_sensor_load<T, W>(f, home_sens[q], py0, n_x, sbx, sby, swx, swy);
       Gt[size_t(f.m) * nb + b] = fused_sensor_sum<T, W>(f, buf, bstride);
     }
     __syncthreads();
+  }
+  // held[k][j] is bin b0 + j - (kFusedBins - nbin)
+  const int nbin = b1 - b0;
+#pragma unroll
+  for (int k = 0; k < HELD; ++k) {
+    const int q = q0 + tid + k * nthr;
+    if (q < q1) {
+      cx<T>* g = Gt + size_t(home_sens[q]) * nb + b0 - (kFusedBins - nbin);
+#pragma unroll
+      for (int j = 0; j < kFusedBins; ++j)
+        if (j >= kFusedBins - nbin) g[j] = held[k][j];
+    }
   }
 }
 
@@ -280,7 +318,7 @@ static hipError_t launch_fused_wvs(const DevPlan& p, const void* V, void* Gt, hi
   if (e != hipSuccess) return e;
   // bins per work-group: enough groups to fill the device several times over
   const long long strips = (p.tiles_y + FS - 1) / FS;
-  int bins = int(std::min<long long>(8, std::max<long long>(1, p.tiles_y * p.nb / 2048)));
+  int bins = int(std::min<long long>(kFusedBins, std::max<long long>(1, p.tiles_y * p.nb / 2048)));
   const int nchunks = (p.nb + bins - 1) / bins;
   const long long blocks = strips * nchunks;
   hipLaunchKernelGGL((k_fft_x_interp<T, W, MAXV, NCT, FS>), dim3((unsigned)blocks), dim3(kFusedThreads * FS), lds, s,
