@@ -115,6 +115,14 @@ def load(path: str = LIB_PATH):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime under the same soname: loading it
+    # first makes the library bind to that one runtime. Loaded the other way
+    # round, torch's tensors and the library's calls would use two runtimes
+    # and the first library call on torch's memory fails.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise OSError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
     lib = C.CDLL(path)

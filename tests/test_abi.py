@@ -145,3 +145,16 @@ def test_batch_count_and_precision_mix_rejected():
     assert lib.pat_batch_create(descs, 65, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_timing_begin(None, 4) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_plan_desc_init(None) == N.PAT_ERR_INVALID_ARGUMENT
+
+
+def test_loader_binds_to_torch_runtime_first():
+    """Loading the library alone (no torch import by the caller) still brings
+    in torch's HIP runtime first, so both use one runtime in the process."""
+    import subprocess
+    import sys
+    code = ("import sys; from paper_1510_01078_amd import _native as N; "
+            "assert 'torch' not in sys.modules; N.load(); "
+            "print('torch' in sys.modules)")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().endswith("True")
