@@ -1,7 +1,8 @@
 """Parity of the compile-time-length FFT kernels (lateral 256/384/512,
 inverse 128/256/512, temporal 2048/2560/4096) against the FP64 oracle on
 small problems chosen so that every instantiated length runs at least once,
-for the reconstruction and the forward model. The benchmark-size tests cover
+for the reconstruction and the forward model, and the x transform once with
+a partial last group of rows. The benchmark-size tests cover
 384/256/2560 at full size; these cover the rest.
 
 Tolerances: FP32 1e-5 relative L2 (the method's FP32 target); FP64 within
@@ -36,6 +37,8 @@ CASES = [
     ((4, 256, 4), 1024, (1e-3, 16e-3, 2e-3), 1.5, dict(ny_over=384, nx_over=8)),
     ((512, 4, 4), 512, (16e-3, 1e-3, 2e-3), 2.0, dict()),                             # inverse x 512
     ((4, 4, 512), 512, (1e-3, 1e-3, 16e-3), 2.0, dict()),                             # inverse z 512 (C2R / R2C)
+    # lateral 256 over 12 grid rows: the x transform's last group of rows is partial (12 = 8 + 4)
+    ((128, 6, 4), 1024, (16e-3, 0.75e-3, 2e-3), 2.0, dict(nx_over=256, ny_over=12)),
 ]
 
 
@@ -46,7 +49,8 @@ def dev():
     return torch.device("cuda", 0)
 
 
-@pytest.mark.parametrize("case", CASES, ids=["x256-t2048", "x512-t4096", "y384", "inv-x512", "inv-z512"])
+@pytest.mark.parametrize("case", CASES, ids=["x256-t2048", "x512-t4096", "y384", "inv-x512", "inv-z512",
+                                              "x256-partial-rows"])
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("fp64", 1e-6)])
 def test_ct_lengths_vs_oracle(dev, case, precision, tol):
     from paper_1510_01078_amd import Plan
