@@ -338,7 +338,7 @@ static hipError_t launch_fused_wv(const DevPlan& p, const void* V, void* Gt, hip
 // rows of up to 512 points need 8 values per lane in the one-wave transform, longer ones 16
 template <typename T, int W>
 static hipError_t launch_fused_w(const DevPlan& p, const void* V, void* Gt, hipStream_t s) {
-  return ct_pick(CtLateral{}, p.n_x, [&](auto c) {
+  return ct_pick(CtFused{}, p.n_x, [&](auto c) {
     constexpr int NCT = decltype(c)::value;
     if constexpr (NCT > 0)
       return launch_fused_wv<T, W, 8, NCT>(p, V, Gt, s);

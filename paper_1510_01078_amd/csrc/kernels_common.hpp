@@ -55,9 +55,14 @@ struct CtList {};
 __host__ __device__ constexpr int ct_maxb(int n, int cap) {
   return n > 0 && kFftMaxV * kFftThreads / n < cap ? kFftMaxV * kFftThreads / n : cap;
 }
-using CtLateral = CtList<256, 384, 512>;
-using CtInverse = CtList<128, 256, 512>;
-using CtTemporal = CtList<2048, 2560, 4096>;
+// 256 / 384 / 512 points: 128^3 .. 256^3 images at oversampling 1.5 or 2;
+// 288 / 192 / 1920: a 192^3 image at oversampling 1.5 with 1536 samples
+using CtLateral = CtList<256, 288, 384, 512>;
+using CtInverse = CtList<128, 192, 256, 512>;
+using CtTemporal = CtList<1920, 2048, 2560, 4096>;
+// the forward model's fused x-FFT + interpolation (instantiated per footprint
+// width and strip height as well) keeps the shorter list
+using CtFused = CtList<256, 384, 512>;
 
 template <class F>
 static inline hipError_t ct_pick(CtList<>, int, F&& f) {
