@@ -292,10 +292,10 @@ __global__ __launch_bounds__(kFusedThreads * FS) void k_fft_x_interp(
   for (int k = 0; k < HELD; ++k) {
     const int q = q0 + tid + k * nthr;
     if (q < q1) {
-      cx<T>* g = Gt + size_t(home_sens[q]) * nb + b0 - (kFusedBins - nbin);
+      cx<T>* g = Gt + size_t(home_sens[q]) * nb + b0;  // bin b0 + i is held[k][i + kFusedBins - nbin]
 #pragma unroll
       for (int j = 0; j < kFusedBins; ++j)
-        if (j >= kFusedBins - nbin) g[j] = held[k][j];
+        if (j >= kFusedBins - nbin) g[j - (kFusedBins - nbin)] = held[k][j];
     }
   }
 }
