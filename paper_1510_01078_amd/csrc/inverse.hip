@@ -81,10 +81,10 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_x(cx<T>* __restrict__ F, i
 
 template <typename T, bool INV, int NCT = 0>
 __device__ __forceinline__ void cfft_y_body(cx<T>* __restrict__ F, int Lh, int lchunk, FftDesc<T> fd, int wm, int bx,
-                                            int by) {
+                                            int by, int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int Ny = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(Ny);
   const int jj = by;
@@ -146,10 +146,10 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_y(cx<T>* __restrict__ F, i
 
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long long nrows, int rows,
-                                           FftDesc<T> fd, T* __restrict__ f, int wm, int bx) {
+                                           FftDesc<T> fd, T* __restrict__ f, int wm, int bx, int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int Nz = NCT > 0 ? NCT : fd.n;
   const int Lh = Nz / 2 + 1;
   const int bstride = lseq(Nz);
@@ -341,7 +341,8 @@ __global__ __launch_bounds__(kFftThreads) void k_cfft_y_inv_batch(const CfftBA* 
     const CfftBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];
     const int by = local / a.gx;
-    cfft_y_body<T, true>(static_cast<cx<T>*>(a.F), a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by);
+    cfft_y_body<T, true>(static_cast<cx<T>*>(a.F), a.Lh, a.lchunk, view_desc<T>(a.fd), 0, local - by * a.gx, by,
+                         loop_lane());
     __syncthreads();
   }
 }
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z_batch(const C2rBA* __rest
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const C2rBA a = batch_args(meta, p);
     c2r_z_body<T>(static_cast<const cx<T>*>(a.F), a.nrows, a.rows, view_desc<T>(a.fd), static_cast<T*>(io.out[p]), 0,
-                  w - meta.prefix[p]);
+                  w - meta.prefix[p]);  // (a re-read lane index raised its registers here)
     __syncthreads();
   }
 }

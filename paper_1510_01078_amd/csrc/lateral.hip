@@ -14,10 +14,11 @@ namespace patk {
 // ---------------------------------------------------------------------------
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
-                                           int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm, int bx, int by) {
+                                           int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm, int bx, int by,
+                                           int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int n_x = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_x);
   const int b = b_begin + by;
@@ -114,10 +115,10 @@ template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_y_body(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                            const T* __restrict__ dcx, const T* __restrict__ dcy,
                                            FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm, int bx, int by,
-                                           const int* __restrict__ jrange = nullptr) {
+                                           const int* __restrict__ jrange = nullptr, int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int n_y = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_y);
   const int jj = by;
@@ -404,7 +405,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __res
     const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     fft_x_body<T>(static_cast<const cx<T>*>(a.U), a.n_y, a.Nx, a.rows, 0, view_desc<T>(a.fd),
-                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by);
+                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by, loop_lane());
     __syncthreads();
   }
 }
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __res
     const int by = local / a.gx;
     fft_y_body<T>(static_cast<const cx<T>*>(a.V), a.nb, a.Nx, a.Ny, a.bins, static_cast<const T*>(a.dcx),
                   static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, local - by * a.gx,
-                  by, a.jrange);
+                  by, a.jrange, loop_lane());
     __syncthreads();
   }
 }

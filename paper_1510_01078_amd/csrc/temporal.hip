@@ -25,10 +25,11 @@ constexpr int temporal_threads() { return NCT > 0 ? kTemporalCtThreads : kTempor
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, int Nt, int n0,
                                               const T* __restrict__ hw, const T* __restrict__ deap,
-                                              FftDesc<T> fd, int b_lo, int nb, cx<T>* __restrict__ Gt, int bx) {
+                                              FftDesc<T> fd, int b_lo, int nb, cx<T>* __restrict__ Gt, int bx,
+                                              int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int nthr = blockDim.x;
   const int n_t = fd.n;
   const int m0 = 2 * bx;  // the pair's first sensor (one pair per group measured fastest on MI355X)
   const bool has1 = m0 + 1 < M;
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kTemporalThreads) void k_temporal_batch(const Tempo
     const TemporalBA a = batch_args(meta, p);
     temporal_body<T>(static_cast<const T*>(io.in[p]), a.M, a.Nt, a.n0, static_cast<const T*>(a.hw),
                      static_cast<const T*>(a.deap), view_desc<T>(a.fd), a.b_lo, a.nb, static_cast<cx<T>*>(a.Gt),
-                     w - meta.prefix[p]);
+                     w - meta.prefix[p], loop_lane());
     __syncthreads();
   }
 }
