@@ -351,9 +351,11 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
     P->range_t = range(deap);
     if (sizeof(T) == 4 && (P->range_xy > 1e4 || P->range_t > 1e4)) return PAT_ERR_UNSUPPORTED;
   }
-  // temporal tap polynomials
+  // temporal tap polynomials: FP64 plans fit them to 1e-13 of the window's
+  // peak, FP32 plans to 2e-8 (a third of FP32's unit roundoff; each degree
+  // fewer is one multiply-add per tap and interpolation point)
   std::vector<double> coef;
-  const double tol = sizeof(T) == 8 ? 1e-13 : 1e-9;
+  const double tol = sizeof(T) == 8 ? 1e-13 : 2e-8;
   int deg = 6;
   for (; deg <= 24; ++deg)
     if (pathost::fit_tap_polynomials(wt, deg, coef) <= tol) break;

@@ -20,6 +20,7 @@ struct TapPoint {
   double cs, sn;
 };
 
+template <typename T>
 __device__ __forceinline__ TapPoint tap_point(double Kabs, double s_per_k, double n0_over_nt, int wt, int b_lo,
                                               int nb) {
   TapPoint tp;
@@ -29,8 +30,19 @@ __device__ __forceinline__ TapPoint tap_point(double Kabs, double s_per_k, doubl
   int base = int(fl) - wt / 2 + 1 - b_lo;
   tp.base = base < 0 ? 0 : (base > nb - wt ? nb - wt : base);
   double q = s * n0_over_nt;
-  q -= floor(q);
-  sincospi(-2.0 * q, &tp.sn, &tp.cs);  // e^{-2 pi i q}; no range reduction needed
+  if constexpr (sizeof(T) == 4) {
+    // FP32 plans round the phase to FP32 anyway: reduce q to [-1/2, 1/2] in
+    // FP64 (its FP32 rounding then errs by at most 3e-8) and take the FP32
+    // sincospi, a fraction of the FP64 one's instructions
+    q -= rint(q);
+    float sn, cs;
+    sincospif(float(-2.0 * q), &sn, &cs);  // e^{-2 pi i q}
+    tp.sn = sn;
+    tp.cs = cs;
+  } else {
+    q -= floor(q);
+    sincospi(-2.0 * q, &tp.sn, &tp.cs);  // e^{-2 pi i q}; no range reduction needed
+  }
   return tp;
 }
 
@@ -115,7 +127,7 @@ __device__ __forceinline__ cx<T> gather_point(const cx<T>* __restrict__ Gh, int 
   const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
   double rK;
   const double Kabs = lattice_kabs(Kx, Ky, Kz, rK);
-  const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
+  const TapPoint tp = tap_point<T>(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
   const T y = T(tp.y);
   const cx<T>* src = Gh + col * nb + tp.base;
   const cx<T>* src2 = Gh + ((long long)((Nx - jj) % Nx) * Ny + (Ny - kk) % Ny) * nb + tp.base;
@@ -399,7 +411,7 @@ __global__ __launch_bounds__(256) void k_scatter(const cx<T>* __restrict__ Dh, i
     const double Kx = j * kxu, Ky = k * kyu, Kz = l * kzu;
     double rK;
     const double Kabs = lattice_kabs(Kx, Ky, Kz, rK);
-    const TapPoint tp = tap_point(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
+    const TapPoint tp = tap_point<T>(Kabs, s_per_k, n0_over_nt, wt, b_lo, nb);
     const T y = T(tp.y);
     {
       T v[WT];
