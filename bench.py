@@ -64,9 +64,10 @@ def spread_bytes(plan, p, eb):
 
 def stage_bytes(plan, p, eb):
     """Algorithmic bytes per launch of every stage (one pass over each array
-    it must touch). The y-FFT and the interpolation count only the (x-mode,
-    band bin) pairs inside the per-x-mode ranges the interpolation reads
-    (plan info band_pairs); the bins outside are neither transformed nor read."""
+    it must touch). The x-FFT's output, the y-FFT and the interpolation count
+    only the (x-mode, band bin) pairs inside the per-x-mode ranges the
+    interpolation reads (plan info band_pairs); the bins outside are neither
+    written, transformed nor read."""
     info = plan.info
     nb, nxo, nyo = info["band_bins"], info["nx_over"], info["ny_over"]
     pairs = info["band_pairs"]
@@ -76,7 +77,7 @@ def stage_bytes(plan, p, eb):
     return [
         p.m * p.nt * eb + p.m * nb * c,                       # temporal: traces in, band out
         spread_bytes(plan, p, eb),                            # spread
-        nb * nyo * nxo * c + nb * Nx * nyo * c,               # FFT along x with crop
+        nb * nyo * nxo * c + pairs * nyo * c,                 # FFT along x with crop (band pairs written)
         pairs * nyo * c + pairs * Ny * c,                     # FFT along y, crop, deconvolve (ranges only)
         pairs * Ny * c + Nx * Ny * lh * c,                    # gather + weight + inverse x pass (one write)
         3 * Nx * Ny * lh * c + Nx * Ny * Nz * eb,             # inverse y pass (read + write), z pass (read, write f)

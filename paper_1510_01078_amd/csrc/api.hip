@@ -373,8 +373,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   // base(s) .. base(s) + w_t - 1 with s = |K| s_per_k non-decreasing in |k| and
   // l, so x-mode j needs base(s(j,0,0)) .. base(s(j,Ny/2,Nz/2)) + w_t - 1; one
   // bin of margin on each side (host and device may round |K| apart), widened
-  // to whole groups of the y-FFT's bins. The y-FFT skips the rest (skipping
-  // the x-FFT's writes there measured slower: the stores lose their full lines).
+  // to whole groups of the y-FFT's bins. The compile-time x-FFT writes and
+  // the y-FFT transforms only these (x mode, bin) pairs.
   std::vector<int> jr(2 * size_t(d.nx));
   {
     const int ybins = patk::fft_batch<T>(dp.n_y, patk::kFftThreads, patk::kFftCap);

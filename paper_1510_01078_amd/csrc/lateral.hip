@@ -15,7 +15,7 @@ namespace patk {
 template <typename T, int NCT = 0>
 __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
                                            int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm, int bx, int by,
-                                           int tid = threadIdx.x) {
+                                           const int* __restrict__ brange = nullptr, int tid = threadIdx.x) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int nthr = blockDim.x;
@@ -42,12 +42,22 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
     __syncthreads();
     fft_ct<T, NCT, kFftThreads, ROWS, false>(buf, nr, twl, tid);
     __syncthreads();
-    // V[b][jj][py0 + r]: neighbouring threads write neighbouring rows
+    // V[b][jj][py0 + r]: neighbouring threads write neighbouring rows; only
+    // the x modes whose band range holds bin b (|j| in [J0, J1]): the y-FFT
+    // and the interpolation read no others
+    const int J0 = brange ? brange[2 * b] : 0, J1 = brange ? brange[2 * b + 1] : Nx;
+    auto kept = [&](int jj) {
+      const int aj = jj < Nx / 2 ? jj : Nx - jj;
+      return aj >= J0 && aj <= J1;
+    };
     cx<T>* d0 = dst + size_t(tid / ROWS) * n_y + tid % ROWS;
     const size_t step = size_t(kFftThreads / ROWS) * n_y;
     staged_cols<ROWS, kFftThreads, (NCT * ROWS + kFftThreads - 1) / kFftThreads>(  // Nx < n_x = NCT
-        Nx, nr, tid, [&](int jj, int r, int) { return buf[r * BS + slot(jj)]; },
-        [&](int, int, int u, cx<T> v) { d0[u * step] = v; });
+        Nx, nr, tid,
+        [&](int jj, int r, int) { return kept(jj) ? buf[r * BS + slot(jj)] : cx<T>{T(0), T(0)}; },
+        [&](int jj, int, int u, cx<T> v) {
+          if (kept(jj)) d0[u * step] = v;
+        });
   } else {
     const FastDiv div_nx(n_x), div_nr(nr);
     staged_copy<kFftMaxV>(
@@ -76,11 +86,12 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
 
 template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_x(const cx<T>* __restrict__ U, int n_y, int Nx, int rows,
-                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm) {
+                                                     int b_begin, FftDesc<T> fd, cx<T>* __restrict__ V, int wm,
+                                                     const int* __restrict__ brange) {
   // neighbouring groups write the two halves of each 128-byte output line:
   // keep them on one XCD so its L2 merges the halves
   const int gl = xcd_linear();
-  fft_x_body<T, NCT>(U, n_y, Nx, rows, b_begin, fd, V, wm, gl % gridDim.x, gl / gridDim.x);
+  fft_x_body<T, NCT>(U, n_y, Nx, rows, b_begin, fd, V, wm, gl % gridDim.x, gl / gridDim.x, brange);
 }
 
 template <typename T>
@@ -98,7 +109,7 @@ hipError_t launch_fft_x(const DevPlan& p, const void* U, void* V, int b_begin, i
     if (e != hipSuccess) return e;
     dim3 grid((p.n_y + rows - 1) / rows, b_end - b_begin);
     hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(U), p.n_y, p.Nx, rows,
-                       b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave);
+                       b_begin, as_desc<T>(p.f_nx), static_cast<cx<T>*>(V), cfg.wave, p.brange);
     return hipGetLastError();
   };
   return ct_pick(CtLateral{}, p.n_x, [&](auto c) { return go(&k_fft_x<T, decltype(c)::value>, decltype(c)::value); });
@@ -405,7 +416,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __res
     const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     fft_x_body<T>(static_cast<const cx<T>*>(a.U), a.n_y, a.Nx, a.rows, 0, view_desc<T>(a.fd),
-                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by, loop_lane());
+                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by, nullptr, loop_lane());
     __syncthreads();
   }
 }
