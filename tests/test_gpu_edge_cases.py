@@ -2,7 +2,8 @@
 the smallest problem (one sensor, two samples, 4^3 grid), sensors on the
 plane's boundary, the longest temporal FFT (n_t = 8192) and the deepest grid
 (Nz = 2048, the forward model's largest per-column LDS), the narrowest and
-widest windows and the extreme oversampling factors, and all-zero inputs.
+widest windows and the extreme oversampling factors, all-zero inputs, and
+spread and x-FFT in rounds of bins against one round (bit for bit).
 
 Tolerances: FP32 1e-5 relative L2 where the window setting can reach it;
 the FP64 form must match the oracle within a frozen bound over its measured
@@ -171,3 +172,33 @@ def test_zero_inputs_give_exact_zeros(dev):
     torch.cuda.synchronize()
     pl.close()
     assert all(bool((o == 0).all()) for o in outs)
+
+
+def test_bin_rounds_give_the_same_bits(dev):
+    """Spread and x-FFT in rounds of 32 band bins through a smaller grid buffer
+    (PATNUFFT_CHUNK_BINS, read when the plan is made) give the one-round
+    reconstruction and adjoint bit for bit: every round's x-FFT writes exactly
+    the x modes whose range holds its bins, as one round does."""
+    import os
+    from paper_1510_01078_amd import Plan
+    p = inputs.config_problem(1)
+    kw = dict(precision="fp32", kernel="kaiser_bessel", sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+    g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, torch.float32)
+    outs, rounds = [], []
+    for chunk in (None, "32"):
+        if chunk is None:
+            os.environ.pop("PATNUFFT_CHUNK_BINS", None)
+        else:
+            os.environ["PATNUFFT_CHUNK_BINS"] = chunk
+        try:
+            pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, **kw)
+        finally:
+            os.environ.pop("PATNUFFT_CHUNK_BINS", None)
+        rounds.append(pl.info["rounds"])
+        outs.append((pl.reconstruct(g), pl.adjoint(g)))
+        torch.cuda.synchronize()
+        pl.close()
+    _say(f"[gpu] rounds {rounds}: reconstruction equal {torch.equal(outs[0][0], outs[1][0])}, "
+         f"adjoint equal {torch.equal(outs[0][1], outs[1][1])}")
+    assert rounds[0] == 1 and rounds[1] > 1
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
