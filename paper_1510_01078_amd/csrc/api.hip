@@ -398,6 +398,15 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   P->band_pairs = 0;
   for (int jj = 0; jj < d.nx; ++jj) P->band_pairs += jr[2 * jj + 1] - jr[2 * jj] + 1;
   const size_t o_jr = blob.add(jr.data(), jr.size() * sizeof(int));
+  // the y-FFT's (x mode, bin group) work items inside the ranges, x-mode
+  // major: its grid holds these only (no work-groups that would return at once)
+  std::vector<int> yl;
+  {
+    const int ybins = patk::fft_batch<T>(dp.n_y, patk::kFftThreads, patk::kFftCap);
+    for (int jj = 0; jj < d.nx; ++jj)
+      for (int b = jr[2 * jj]; b <= jr[2 * jj + 1]; b += ybins) yl.push_back(jj << 16 | (b / ybins));
+  }
+  const size_t o_yl = blob.add(yl.data(), std::max<size_t>(1, yl.size()) * sizeof(int));
   // the same ranges per bin: both ends are non-decreasing in |j|, so the
   // x-modes that hold bin b are J0(b) <= |j| <= J1(b) (J0 > J1: none)
   std::vector<int> br(2 * size_t(dp.nb));
@@ -453,6 +462,8 @@ pat_status build_tables(pat_plan* P, hipStream_t stream) {
   dp.dcy = at(o_dcy);
   dp.hcoef = at(o_hc);
   dp.jrange = static_cast<const int*>(at(o_jr));
+  dp.ylist = static_cast<const int*>(at(o_yl));
+  dp.ylist_n = int(yl.size());
   dp.brange = static_cast<const int*>(at(o_br));
   dp.f_nt.tw = at(o_tw_nt);
   dp.f_nx.tw = at(o_tw_nx);
@@ -565,6 +576,8 @@ pat_status run_image_in(pat_plan* P, const void* f, void* g, void* ws, hipStream
   if (!P->forward_fused) {
     dp.jrange = nullptr;
     dp.brange = nullptr;
+    dp.ylist = nullptr;
+    dp.ylist_n = 0;
   }
   unsigned char* A = static_cast<unsigned char*>(ws);
   unsigned char* B = A + P->off_B;

@@ -133,8 +133,10 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     const int bins = patk::fft_batch<T>(d.n_y, cfg.threads, cfg.cap);
     if (bins * d.n_y > kFft || bins * d.Ny > kFft) return PAT_ERR_UNSUPPORTED;
     const int gx3 = (d.nb + bins - 1) / bins;
-    a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A, d.jrange};
-    pre[3][p + 1] = gx3 * d.Nx;
+    const bool listed = d.ylist && d.ylist_n > 0 && d.jrange;
+    a3[p] = patk::FftYBA{Bw, d.dcx, d.dcy, patk::as_view(d.f_ny), d.nb, d.Nx, d.Ny, bins, gx3, A, d.jrange,
+                         listed ? d.ylist : nullptr};
+    pre[3][p + 1] = listed ? d.ylist_n : gx3 * d.Nx;
     lds[3] = std::max(lds[3], (size_t(bins) * patk::lseq(d.n_y) + d.n_y) * c);
     // stage 4: temporal interpolation and weight (image-ready spectrum) fused
     // with the inverse transform along x

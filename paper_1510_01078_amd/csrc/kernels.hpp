@@ -63,6 +63,8 @@ struct DevPlan {
   const int* jrange = nullptr;    // [Nx][2] first and last band bin the interpolation reads per x-mode,
                                   // in whole groups of the y-FFT's bins; the y-FFT skips the others
   const int* brange = nullptr;    // [nb][2] per band bin the smallest and largest |j| whose range holds it
+  const int* ylist = nullptr;     // the y-FFT's work items inside the ranges: jj << 16 | bin group
+  int ylist_n = 0;
   const void* dcx = nullptr;      // [Nx] 1/phihat(j/n_x), 0 at j = -Nx/2
   const void* dcy = nullptr;      // [Ny]
   const void* hcoef = nullptr;    // [w_t][hdeg+1] temporal tap polynomials
@@ -178,6 +180,7 @@ struct FftXBA {
 struct FftYBA {
   const void* V; const void* dcx; const void* dcy; FftView fd; int nb, Nx, Ny, bins, gx; void* Gh;
   const int* jrange;  // per x-mode band range (bin groups outside it are skipped)
+  const int* ylist;   // the work items inside the ranges (jj << 16 | bin group), or nullptr: gx * Nx items
 };
 struct GatherBA {  // the gather fused with the inverse transform along x
   const void* Gh; const void* hcoef; int nb, b_lo, Nx, Ny, Nz, wt, deg;

@@ -203,11 +203,17 @@ template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y(const cx<T>* __restrict__ V, int nb, int Nx, int Ny, int bins,
                                                      const T* __restrict__ dcx, const T* __restrict__ dcy,
                                                      FftDesc<T> fd, cx<T>* __restrict__ Gh, int wm,
-                                                     const int* __restrict__ jrange) {
+                                                     const int* __restrict__ jrange, const int* __restrict__ ylist) {
   // neighbouring groups write the two halves of each 128-byte output line:
   // keep them on one XCD so its L2 merges the halves
   const int gl = xcd_linear();
-  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, gl % gridDim.x, gl / gridDim.x, jrange);
+  int bx = gl % gridDim.x, by = gl / gridDim.x;
+  if (ylist) {  // one-dimensional grid over the work items inside the ranges
+    const int e = ylist[gl];
+    by = e >> 16;
+    bx = e & 0xffff;
+  }
+  fft_y_body<T, NCT>(V, nb, Nx, Ny, bins, dcx, dcy, fd, Gh, wm, bx, by, jrange);
 }
 
 template <typename T>
@@ -222,10 +228,11 @@ hipError_t launch_fft_y(const DevPlan& p, const void* V, void* Gh, hipStream_t s
     if (nct > 0 && (bins != ct_maxb(nct, kFftCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
-    dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+    const bool listed = p.ylist && p.ylist_n > 0 && p.jrange;
+    const dim3 grid = listed ? dim3(p.ylist_n) : dim3((p.nb + bins - 1) / bins, p.Nx);
     hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(V), p.nb, p.Nx, p.Ny,
                        bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                       static_cast<cx<T>*>(Gh), cfg.wave, p.jrange);
+                       static_cast<cx<T>*>(Gh), cfg.wave, p.jrange, listed ? p.ylist : nullptr);
     return hipGetLastError();
   };
   return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y<T, decltype(c)::value>, decltype(c)::value); });
@@ -241,14 +248,17 @@ template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_fft_y_t(const cx<T>* __restrict__ Gh, int nb, int Nx, int Ny,
                                                        int bins, const T* __restrict__ dcx,
                                                        const T* __restrict__ dcy, FftDesc<T> fd,
-                                                       cx<T>* __restrict__ V, const int* __restrict__ jrange) {
+                                                       cx<T>* __restrict__ V, const int* __restrict__ jrange,
+                                                       const int* __restrict__ ylist) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cx<T>* buf = reinterpret_cast<cx<T>*>(smem_raw);
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int n_y = NCT > 0 ? NCT : fd.n;
   const int bstride = lseq(n_y);
-  const int jj = blockIdx.y;  // (an XCD-grouped order measured slower here)
-  const int b0 = blockIdx.x * bins;
+  // (an XCD-grouped order measured slower here); with ylist a one-dimensional
+  // grid over the work items inside the ranges
+  const int jj = ylist ? ylist[blockIdx.x] >> 16 : int(blockIdx.y);
+  const int b0 = (ylist ? ylist[blockIdx.x] & 0xffff : int(blockIdx.x)) * bins;
   const int nbc = min(bins, nb - b0);
   // bins outside the x-mode's range hold zeros that nothing reads: skipped
   if (jrange && (b0 + nbc - 1 < jrange[2 * jj] || b0 > jrange[2 * jj + 1])) return;
@@ -334,10 +344,11 @@ hipError_t launch_fft_y_t(const DevPlan& p, const void* Gh, void* V, hipStream_t
     if (nct > 0 && (bins != ct_maxb(nct, kFftCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(kern), lds);
     if (e != hipSuccess) return e;
-    dim3 grid((p.nb + bins - 1) / bins, p.Nx);
+    const bool listed = p.ylist && p.ylist_n > 0 && p.jrange;
+    const dim3 grid = listed ? dim3(p.ylist_n) : dim3((p.nb + bins - 1) / bins, p.Nx);
     hipLaunchKernelGGL(kern, grid, dim3(cfg.threads), lds, s, static_cast<const cx<T>*>(Gh), p.nb, p.Nx, p.Ny,
                        bins, static_cast<const T*>(p.dcx), static_cast<const T*>(p.dcy), as_desc<T>(p.f_ny),
-                       static_cast<cx<T>*>(V), p.jrange);
+                       static_cast<cx<T>*>(V), p.jrange, listed ? p.ylist : nullptr);
     return hipGetLastError();
   };
   return ct_pick(CtLateral{}, p.n_y, [&](auto c) { return go(&k_fft_y_t<T, decltype(c)::value>, decltype(c)::value); });
@@ -432,10 +443,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_y_batch(const FftYBA* __res
     const int p = __builtin_amdgcn_readfirstlane(batch_locate(meta.prefix, nprob, w));
     const FftYBA a = batch_args(meta, p);
     const int local = w - meta.prefix[p];
-    const int by = local / a.gx;
+    int by = local / a.gx, bx = local - by * a.gx;
+    if (a.ylist) {  // the problem's work items inside its ranges
+      const int e = a.ylist[local];
+      by = e >> 16;
+      bx = e & 0xffff;
+    }
     fft_y_body<T>(static_cast<const cx<T>*>(a.V), a.nb, a.Nx, a.Ny, a.bins, static_cast<const T*>(a.dcx),
-                  static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, local - by * a.gx,
-                  by, a.jrange, loop_lane());
+                  static_cast<const T*>(a.dcy), view_desc<T>(a.fd), static_cast<cx<T>*>(a.Gh), 0, bx, by, a.jrange,
+                  loop_lane());
     __syncthreads();
   }
 }
