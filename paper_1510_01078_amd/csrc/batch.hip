@@ -117,7 +117,7 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     // stage 0: temporal FFT, one block per sensor pair
     a0[p] = patk::TemporalBA{d.hw, d.deap, patk::as_view(d.f_nt), d.M, d.Nt, d.n0, d.b_lo, d.nb, C};
     pre[0][p + 1] = (d.M + 1) / 2;
-    lds[0] = std::max(lds[0], size_t(patk::lseq(d.n_t)) * c);
+    lds[0] = std::max(lds[0], size_t(patk::temporal_lds_slots(d.n_t)) * c);
     // stage 1: spread, all bins in one round
     const int nchunks = (d.nb + 15) / 16;
     a1[p] = patk::SpreadBA{C, d.slot_off, d.slot_sens, d.slot_w, d.slot_k, d.nb, d.n_x, d.n_y, d.tiles_x, nchunks, A};

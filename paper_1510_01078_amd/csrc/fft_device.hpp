@@ -68,6 +68,40 @@ struct FftDesc {
   const cx<T>* tw;
 };
 
+// Twiddle sources w(t) = exp(-2*pi*i*t/n), 0 <= t < n, for the passes below.
+// TwTable reads a full table (global memory or a copy in LDS). TwSplit
+// multiplies two short LDS tables, w(t) = w(64*(t >> 6)) * w(t & 63): n/64 +
+// 64 entries instead of n (832 bytes instead of 20 KiB at 2560 points), for
+// one complex multiply more per twiddle and about one more rounding.
+template <typename T>
+struct TwTable {
+  const cx<T>* tw;
+  __device__ __forceinline__ cx<T> operator()(int t) const { return tw[t]; }
+};
+
+template <typename T>
+struct TwSplit {
+  const cx<T>* hi;  // hi[u] = w(64 u), u < ceil(n / 64)
+  const cx<T>* lo;  // lo[v] = w(v), v < min(n, 64)
+  __device__ __forceinline__ cx<T> operator()(int t) const { return cmul(hi[t >> 6], lo[t & 63]); }
+};
+
+// Entries of the split tables of an n-point transform.
+__host__ __device__ constexpr int tw_split_slots(int n) { return (n + 63) / 64 + 64; }
+
+// Fill the split tables at `slots` (tw_split_slots(n) entries) from the full
+// table; the caller's next barrier publishes them.
+template <typename T>
+__device__ __forceinline__ TwSplit<T> tw_split_fill(cx<T>* slots, const cx<T>* __restrict__ tw, int n, int tid,
+                                                    int nthr) {
+  const int nh = (n + 63) / 64;
+  for (int i = tid; i < nh + 64; i += nthr) {
+    if (i < nh) slots[i] = tw[64 * i];
+    else if (i - nh < n) slots[i] = tw[i - nh];
+  }
+  return TwSplit<T>{slots, slots + nh};
+}
+
 __device__ __forceinline__ int fdiv(int x, uint32_t m) { return m ? int(__umulhi(uint32_t(x), m)) : x; }
 
 // Exact x / d for 0 <= x, d < 2^16 by a multiply-high (the multiplier is
@@ -282,9 +316,9 @@ __device__ __forceinline__ void fft_sync() {
 
 // One radix-R Stockham pass over `batch` sequences; every thread holds at
 // most MAXV values, so batch*n <= MAXV*nthr is required (and batch*n < 2^16).
-template <typename T, int R, int MAXV, bool INV, bool WAVE = false>
-__device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int batch, int bstride,
-                                              const cx<T>* __restrict__ tw, int tid, int nthr) {
+template <typename T, int R, int MAXV, bool INV, bool WAVE, typename TW>
+__device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int batch, int bstride, TW tw, int tid,
+                                              int nthr) {
   constexpr int K = (MAXV + R - 1) / R;
   const int nbf = ps.nbf;
   const int p = ps.p;
@@ -304,7 +338,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int
         const int ts = k * ps.twstep;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[r * ts];
+          cx<T> w = tw(r * ts);
           if (INV) w.y = -w.y;
           v[it][r] = cmul(v[it][r], w);
         }
@@ -333,19 +367,25 @@ __device__ __forceinline__ void stockham_pass(cx<T>* buf, const FftPass& ps, int
 // cooperate on `batch` sequences and callers must __syncthreads() after
 // filling buf; with WAVE = true the 64 lanes of one wave (tid = lane,
 // nthr = 64) own the sequences and only wave-local ordering is used.
-template <typename T, int MAXV, bool INV, bool WAVE = false>
-__device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int batch, int bstride, int tid, int nthr) {
+template <typename T, int MAXV, bool INV, bool WAVE, typename TW>
+__device__ __forceinline__ void fft_lds_tw(cx<T>* buf, const FftDesc<T> fd, TW tw, int batch, int bstride, int tid,
+                                           int nthr) {
   for (int s = 0; s < fd.npass; ++s) {
     const FftPass ps = fd.pass[s];
     switch (ps.R) {
-      case 8: stockham_pass<T, 8, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 4: stockham_pass<T, 4, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 2: stockham_pass<T, 2, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 3: stockham_pass<T, 3, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      case 6: stockham_pass<T, 6, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
-      default: stockham_pass<T, 5, MAXV, INV, WAVE>(buf, ps, batch, bstride, fd.tw, tid, nthr); break;
+      case 8: stockham_pass<T, 8, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
+      case 4: stockham_pass<T, 4, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
+      case 2: stockham_pass<T, 2, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
+      case 3: stockham_pass<T, 3, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
+      case 6: stockham_pass<T, 6, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
+      default: stockham_pass<T, 5, MAXV, INV, WAVE>(buf, ps, batch, bstride, tw, tid, nthr); break;
     }
   }
+}
+
+template <typename T, int MAXV, bool INV, bool WAVE = false>
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const FftDesc<T> fd, int batch, int bstride, int tid, int nthr) {
+  fft_lds_tw<T, MAXV, INV, WAVE>(buf, fd, TwTable<T>{fd.tw}, batch, bstride, tid, nthr);
 }
 
 // ---------------------------------------------------------------------------
@@ -385,8 +425,8 @@ __host__ __device__ constexpr int ct_prefix(int n, int s) {
   return p;
 }
 
-template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE>
-__device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE, typename TW>
+__device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, TW tw, int tid) {
   constexpr CtPlan pl = ct_plan(N);
   constexpr int R = pl.r[S];
   constexpr int P = ct_prefix(N, S);
@@ -429,7 +469,7 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
           const int ts = k * TWS;
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            cx<T> w = tw[r * ts];
+            cx<T> w = tw(r * ts);
             if (INV) w.y = -w.y;
             v[it][r] = cmul(v[it][r], w);
           }
@@ -473,19 +513,25 @@ __device__ __forceinline__ void ct_pass(cx<T>* buf, int batch, const cx<T>* __re
   fft_sync<WAVE>();
 }
 
-template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE>
-__device__ __forceinline__ void ct_passes(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+template <typename T, int N, int S, int NT, int MAXB, bool INV, bool WAVE, typename TW>
+__device__ __forceinline__ void ct_passes(cx<T>* buf, int batch, TW tw, int tid) {
   if constexpr (S < ct_plan(N).np) {
     ct_pass<T, N, S, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
     ct_passes<T, N, S + 1, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
   }
 }
 
-// Transform `batch` (<= MAXB) sequences of length N at buf + f*lseq(N).
-template <typename T, int N, int NT, int MAXB, bool INV, bool WAVE = false>
-__device__ __forceinline__ void fft_ct(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+// Transform `batch` (<= MAXB) sequences of length N at buf + f*lseq(N),
+// twiddles from the source tw (fft_ct: a full table).
+template <typename T, int N, int NT, int MAXB, bool INV, bool WAVE = false, typename TW>
+__device__ __forceinline__ void fft_ct_tw(cx<T>* buf, int batch, TW tw, int tid) {
   static_assert(ct_prefix(N, ct_plan(N).np) == N, "length must factor into 2, 3, 5");
   ct_passes<T, N, 0, NT, MAXB, INV, WAVE>(buf, batch, tw, tid);
+}
+
+template <typename T, int N, int NT, int MAXB, bool INV, bool WAVE = false>
+__device__ __forceinline__ void fft_ct(cx<T>* buf, int batch, const cx<T>* __restrict__ tw, int tid) {
+  fft_ct_tw<T, N, NT, MAXB, INV, WAVE>(buf, batch, TwTable<T>{tw}, tid);
 }
 
 }  // namespace patk

@@ -204,6 +204,10 @@ __device__ __forceinline__ int batch_locate(const int* prefix, int nprob, int w)
   return lo;
 }
 
+// LDS slots of one temporal work-group (a sensor pair): the sequence, then
+// the split twiddle tables (single-problem and batched launches).
+__host__ __device__ constexpr int temporal_lds_slots(int n_t) { return lseq(n_t) + tw_split_slots(n_t); }
+
 // The lane index, re-read inside a batched stage's persistent loop: values
 // computed from it are then not hoisted out of the loop, where they stayed
 // live across every work item (the batched temporal FFT held 94 registers

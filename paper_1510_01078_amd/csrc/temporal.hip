@@ -13,8 +13,12 @@ namespace patk {
 // Two real traces share one complex FFT (re = sensor m0, im = sensor m1).
 // Sample n sits at index (n - n0) mod n_t after multiplication by
 // h_m*dt/phihat_t((n - n0)/n_t) (hw == nullptr: unit weight instead of
-// h_m*dt); bins b_lo .. b_lo+nb-1 are kept per sensor.
+// h_m*dt); bins b_lo .. b_lo+nb-1 are kept per sensor. The transform's
+// twiddles come from the split tables (TwSplit) in LDS behind the sequence:
+// the full 2560-point table in LDS cost work-groups per CU, read from global
+// memory it left every pass waiting on it (0.096 -> 0.083 ms at 2560 points).
 // ---------------------------------------------------------------------------
+
 constexpr int kTemporalThreads = 512;
 // compile-time lengths (at most 4096 points): 256 threads, 16 values each,
 // measured 5 % faster than 512 at 2560 points
@@ -41,6 +45,7 @@ __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, in
     if (pos < 0) pos += n_t;
     buf[lpos(pos)] = cx<T>{T(0), T(0)};
   }
+  const TwSplit<T> tw = tw_split_fill(buf + lseq(n_t), fd.tw, n_t, tid, nthr);
   const T w0 = hw ? hw[m0] : T(1);
   const T w1 = has1 ? (hw ? hw[m0 + 1] : T(1)) : T(0);
   const T* g0 = g + size_t(m0) * Nt;
@@ -60,9 +65,9 @@ __device__ __forceinline__ void temporal_body(const T* __restrict__ g, int M, in
       });
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, temporal_threads<NCT>(), 1, false>(buf, 1, fd.tw, tid);
+    fft_ct_tw<T, NCT, temporal_threads<NCT>(), 1, false>(buf, 1, tw, tid);
   else
-    fft_lds<T, kFftMaxV, false>(buf, fd, 1, lseq(n_t), tid, nthr);
+    fft_lds_tw<T, kFftMaxV, false, false>(buf, fd, tw, 1, lseq(n_t), tid, nthr);
   for (int i = tid; i < nb; i += nthr) {
     const int b = b_lo + i;  // -n_t < b < n_t (the band fits in n_t bins)
     const int pb = b < 0 ? b + n_t : b;
@@ -87,7 +92,7 @@ template <typename T>
 hipError_t launch_temporal(const DevPlan& p, const T* g, void* Gt, bool weighted, hipStream_t s) {
   if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t) return hipErrorInvalidValue;
   const int blocks = (p.M + 1) / 2;  // one sensor pair per group
-  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
+  const size_t lds = size_t(temporal_lds_slots(p.n_t)) * sizeof(cx<T>);
   return ct_pick(CtTemporal{}, p.n_t, [&](auto c) {
     constexpr int NCT = decltype(c)::value, NT = temporal_threads<NCT>();
     static_assert(NCT <= kFftMaxV * NT, "a thread holds at most kFftMaxV values");
@@ -120,6 +125,7 @@ __global__ __launch_bounds__(temporal_threads<NCT>()) void k_temporal_t(const cx
   const int m0 = 2 * blockIdx.x;
   const bool has1 = m0 + 1 < M;
   for (int q = tid; q < n_t; q += nthr) buf[lpos(q)] = cx<T>{T(0), T(0)};
+  const TwSplit<T> tw = tw_split_fill(buf + lseq(n_t), fd.tw, n_t, tid, nthr);
   __syncthreads();
   const cx<T>* x0 = Gt + size_t(m0) * nb;
   const cx<T>* x1 = Gt + size_t(m0 + 1) * nb;
@@ -140,9 +146,9 @@ __global__ __launch_bounds__(temporal_threads<NCT>()) void k_temporal_t(const cx
   }
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, temporal_threads<NCT>(), 1, true>(buf, 1, fd.tw, tid);
+    fft_ct_tw<T, NCT, temporal_threads<NCT>(), 1, true>(buf, 1, tw, tid);
   else
-    fft_lds<T, kFftMaxV, true>(buf, fd, 1, lseq(n_t), tid, nthr);
+    fft_lds_tw<T, kFftMaxV, true, false>(buf, fd, tw, 1, lseq(n_t), tid, nthr);
   __syncthreads();
   for (int n = tid; n < Nt; n += nthr) {
     int pos = n - n0;
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(temporal_threads<NCT>()) void k_temporal_t(const cx
 template <typename T>
 hipError_t launch_temporal_t(const DevPlan& p, const void* Gt, T* g, hipStream_t s) {
   if (p.n_t > kFftMaxV * kTemporalThreads || p.Nt > p.n_t || p.nb > p.n_t) return hipErrorInvalidValue;
-  const size_t lds = size_t(lseq(p.n_t)) * sizeof(cx<T>);
+  const size_t lds = size_t(temporal_lds_slots(p.n_t)) * sizeof(cx<T>);
   return ct_pick(CtTemporal{}, p.n_t, [&](auto c) {
     constexpr int NCT = decltype(c)::value, NT = temporal_threads<NCT>();
     static_assert(NCT <= kFftMaxV * NT, "a thread holds at most kFftMaxV values");
