@@ -309,6 +309,14 @@ pat_status pat_reconstruct_noalloc(pat_plan* plan, const void* g, void* f, void*
  * interpolation kernel counts under stage 1 and stage 2 reads 0. */
 #define PAT_TIMING_STAGES 6
 pat_status pat_timing_begin(pat_plan* plan, int32_t max_calls);
+/* The same for the stages in stage_mask only (bit s = stage s, nonzero,
+ * below 1 << PAT_TIMING_STAGES): events are recorded only at the two ends
+ * of those stages, so the other kernels run back to back as in an untimed
+ * call (every event between two kernels costs a few microseconds), and
+ * pat_timing_end reports 0 for the other stages. pat_timing_begin is this
+ * call with every stage's bit set. PAT_ERR_INVALID_ARGUMENT for a mask
+ * outside that range. */
+pat_status pat_timing_begin_stages(pat_plan* plan, int32_t max_calls, uint32_t stage_mask);
 pat_status pat_timing_end(pat_plan* plan, double* ms, int32_t nstage, int32_t* calls);
 
 const char* pat_status_str(pat_status status);

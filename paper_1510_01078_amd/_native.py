@@ -101,6 +101,7 @@ SIGNATURES = {
     "pat_batch_reconstruct": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_void_p]),
     "pat_batch_destroy": (C.c_int, [C.c_void_p]),
     "pat_timing_begin": (C.c_int, [C.c_void_p, C.c_int32]),
+    "pat_timing_begin_stages": (C.c_int, [C.c_void_p, C.c_int32, C.c_uint32]),
     "pat_timing_end": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
     "pat_status_str": (C.c_char_p, [C.c_int]),
     "pat_version": (C.c_char_p, []),

@@ -514,14 +514,18 @@ struct Marker {
   int call;
   int next = 0;
   hipStream_t s;
-  // record the next event of this call; `stage` names the work since the previous one
-  void operator()(int stage) {
-    if (call < 0 || next >= P->marks_per_call) return;
+  // boundary between stage `done` (the work since the previous boundary; -1
+  // at the call's start) and stage `after` (-1 at its end): an event is
+  // recorded where either is timed, so a timed stage always lies between two
+  // consecutive events of the call
+  void operator()(int done, int after) {
+    if (call < 0 || next >= P->marks_per_call || !(timed(done) || timed(after))) return;
     const size_t i = size_t(call) * P->marks_per_call + next;
-    P->ev_stage[i] = stage;
+    P->ev_stage[i] = done;
     (void)hipEventRecord(P->ev[i], s);
     ++next;
   }
+  bool timed(int stage) const { return stage >= 0 && ((P->ev_mask >> stage) & 1u); }
 };
 
 inline int rounds(const patk::DevPlan& dp) { return (dp.nb + dp.chunk_bins - 1) / dp.chunk_bins; }
@@ -538,30 +542,30 @@ pat_status run_traces_in(pat_plan* P, const void* g, void* out, void* ws, hipStr
   unsigned char* C = A + P->off_C;
   Marker mark{P, P->ev_used < P->ev_max ? P->ev_used++ : -1, 0, s};
   hipError_t e;
-  mark(-1);
+  mark(-1, 0);
   if ((e = patk::launch_temporal<T>(dp, static_cast<const T*>(g), C, op != OP_ADJOINT, s)) != hipSuccess)
     return to_status(e);
-  mark(0);
+  mark(0, 1);
   for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
     const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
     if ((e = patk::launch_spread<T>(dp, C, A, b0, b1, s)) != hipSuccess) return to_status(e);
-    mark(1);
+    mark(1, 2);
     if ((e = patk::launch_fft_x<T>(dp, A, B, b0, b1, s)) != hipSuccess) return to_status(e);
-    mark(2);
+    mark(2, b1 < dp.nb ? 1 : 3);
   }
   if ((e = patk::launch_fft_y<T>(dp, B, A, s)) != hipSuccess) return to_status(e);
-  mark(3);
+  mark(3, 4);
   if (op == OP_SPECTRUM) {
     if ((e = patk::launch_gather<T>(dp, A, out, patk::GATHER_PHYSICAL, s)) != hipSuccess) return to_status(e);
-    mark(4);
+    mark(4, -1);
     return PAT_OK;
   }
   // the gather and the inverse transform along x run as one kernel
   const int mode = op == OP_ADJOINT ? patk::GATHER_ADJOINT : patk::GATHER_IMAGE;
   if ((e = patk::launch_gather_x<T>(dp, A, B, mode, s)) != hipSuccess) return to_status(e);
-  mark(4);
+  mark(4, 5);
   if ((e = patk::launch_inverse<T>(dp, B, static_cast<T*>(out), s, true)) != hipSuccess) return to_status(e);
-  mark(5);
+  mark(5, -1);
   return PAT_OK;
 }
 
@@ -585,27 +589,27 @@ pat_status run_image_in(pat_plan* P, const void* f, void* g, void* ws, hipStream
   Marker mark{P, P->ev_used < P->ev_max ? P->ev_used++ : -1, 0, s};
   hipError_t e;
   const int deriv = op == OP_FORWARD_DX ? 1 : (op == OP_FORWARD_DY ? 2 : 0);
-  mark(-1);
+  mark(-1, 5);
   if ((e = patk::launch_forward3d<T>(dp, static_cast<const T*>(f), B, s)) != hipSuccess) return to_status(e);
-  mark(5);
+  mark(5, 4);
   if ((e = patk::launch_scatter<T>(dp, B, A, deriv, s)) != hipSuccess) return to_status(e);
-  mark(4);
+  mark(4, 3);
   if ((e = patk::launch_fft_y_t<T>(dp, A, B, s)) != hipSuccess) return to_status(e);
-  mark(3);
+  mark(3, P->forward_fused ? 1 : 2);
   if (P->forward_fused) {
     if ((e = patk::launch_fft_x_interp<T>(dp, B, C, s)) != hipSuccess) return to_status(e);
-    mark(1);
+    mark(1, 0);
   } else {
     for (int b0 = 0; b0 < dp.nb; b0 += dp.chunk_bins) {
       const int b1 = std::min(dp.nb, b0 + dp.chunk_bins);
       if ((e = patk::launch_fft_x_t<T>(dp, B, A, b0, b1, s)) != hipSuccess) return to_status(e);
-      mark(2);
+      mark(2, 1);
       if ((e = patk::launch_interp<T>(dp, A, C, b0, b1, s)) != hipSuccess) return to_status(e);
-      mark(1);
+      mark(1, b1 < dp.nb ? 2 : 0);
     }
   }
   if ((e = patk::launch_temporal_t<T>(dp, C, static_cast<T*>(g), s)) != hipSuccess) return to_status(e);
-  mark(0);
+  mark(0, -1);
   return PAT_OK;
 }
 
@@ -751,9 +755,15 @@ pat_status pat_forward_dxy(pat_plan* P, const void* f, int32_t axis, void* g, vo
 }
 
 pat_status pat_timing_begin(pat_plan* P, int32_t max_calls) {
-  if (!P || max_calls < 1 || max_calls > 100000) return PAT_ERR_INVALID_ARGUMENT;
+  return pat_timing_begin_stages(P, max_calls, (1u << PAT_TIMING_STAGES) - 1u);
+}
+
+pat_status pat_timing_begin_stages(pat_plan* P, int32_t max_calls, uint32_t stage_mask) {
+  if (!P || max_calls < 1 || max_calls > 100000 || stage_mask == 0 || stage_mask >= (1u << PAT_TIMING_STAGES))
+    return PAT_ERR_INVALID_ARGUMENT;
   DeviceGuard guard(P->device);
   destroy_events(P);
+  P->ev_mask = stage_mask;
   P->marks_per_call = 5 + 2 * rounds(P->dp);
   const size_t n = size_t(max_calls) * P->marks_per_call;
   P->ev.resize(n);
@@ -781,6 +791,7 @@ pat_status pat_timing_end(pat_plan* P, double* ms, int32_t nstage, int32_t* call
     for (int k = 1; k < P->marks_per_call; ++k) {
       const int stage = P->ev_stage[base + k];
       if (stage < 0) break;
+      if (!((P->ev_mask >> stage) & 1u)) continue;  // an untimed stage: its ends need not be events
       float t = 0.f;
       if (hipEventElapsedTime(&t, P->ev[base + k - 1], P->ev[base + k]) != hipSuccess) {
         st = PAT_ERR_HIP;

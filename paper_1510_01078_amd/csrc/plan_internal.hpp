@@ -76,6 +76,7 @@ struct pat_plan {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_stage;
   int marks_per_call = 0;
+  unsigned ev_mask = 0;  // stages whose two ends record events
   int ev_max = 0;
   int ev_used = 0;
 };

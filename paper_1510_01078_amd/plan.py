@@ -225,9 +225,19 @@ class Plan:
         """The sensor positions the plan was built for (host copy, [M, 2])."""
         return self._xy.copy()
 
-    def timing_begin(self, max_calls: int):
+    def timing_begin(self, max_calls: int, stages=None):
+        """Per-stage event timing of the next max_calls compute calls; `stages`
+        (stage indices) limits the events to those stages' ends
+        (pat_timing_begin_stages), None times every stage."""
         self._check_handle()
-        N.check(self._lib.pat_timing_begin(self._handle, int(max_calls)), "pat_timing_begin")
+        if stages is None:
+            N.check(self._lib.pat_timing_begin(self._handle, int(max_calls)), "pat_timing_begin")
+        else:
+            mask = 0
+            for st in stages:
+                mask |= 1 << int(st)
+            N.check(self._lib.pat_timing_begin_stages(self._handle, int(max_calls), mask),
+                    "pat_timing_begin_stages")
 
     def timing_end(self):
         """Returns (per-stage summed milliseconds [6], number of calls recorded)."""

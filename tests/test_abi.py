@@ -144,6 +144,7 @@ def test_batch_count_and_precision_mix_rejected():
     assert lib.pat_batch_create(descs, 0, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_batch_create(descs, 65, 0, None, C.byref(h)) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_timing_begin(None, 4) == N.PAT_ERR_INVALID_ARGUMENT
+    assert lib.pat_timing_begin_stages(None, 4, 2) == N.PAT_ERR_INVALID_ARGUMENT
     assert lib.pat_plan_desc_init(None) == N.PAT_ERR_INVALID_ARGUMENT
 
 

@@ -3,7 +3,8 @@ the smallest problem (one sensor, two samples, 4^3 grid), sensors on the
 plane's boundary, the longest temporal FFT (n_t = 8192) and the deepest grid
 (Nz = 2048, the forward model's largest per-column LDS), the narrowest and
 widest windows and the extreme oversampling factors, all-zero inputs, and
-spread and x-FFT in rounds of bins against one round (bit for bit).
+spread and x-FFT in rounds of bins against one round (bit for bit), and event
+timing limited to chosen stages.
 
 Tolerances: FP32 1e-5 relative L2 where the window setting can reach it;
 the FP64 form must match the oracle within a frozen bound over its measured
@@ -202,3 +203,44 @@ def test_bin_rounds_give_the_same_bits(dev):
          f"adjoint equal {torch.equal(outs[0][1], outs[1][1])}")
     assert rounds[0] == 1 and rounds[1] > 1
     assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_stage_timing_mask(dev):
+    """Event timing limited to chosen stages (pat_timing_begin_stages): the
+    chosen stages get their times, every other stage reads 0, with one round
+    of bins and with several (the spread's rounds are summed), for the
+    reconstruction and the forward model; the image is the untimed one bit for
+    bit; masks of no stage or past the last stage are refused."""
+    import os
+    from paper_1510_01078_amd import Plan, _native as N
+    from paper_1510_01078_amd._native import PatError
+    p = inputs.config_problem(1)
+    kw = dict(precision="fp32", kernel="kaiser_bessel", sigma_xy=1.5, width_xy=8, sigma_t=1.25, width_t=10)
+    g = torch.from_numpy(np.ascontiguousarray(p.g)).to(dev, torch.float32)
+    for chunk in (None, "32"):
+        if chunk is not None:
+            os.environ["PATNUFFT_CHUNK_BINS"] = chunk
+        try:
+            pl = Plan(p.xy, p.nt, p.dt, p.c, p.shape, p.extent, sensor_h=p.h, **kw)
+        finally:
+            os.environ.pop("PATNUFFT_CHUNK_BINS", None)
+        ref = pl.reconstruct(g)
+        for stages in ((1,), (0, 4), tuple(range(N.PAT_TIMING_STAGES))):
+            pl.timing_begin(3, stages=stages)
+            outs = [pl.reconstruct(g) for _ in range(3)]
+            ms, calls = pl.timing_end()
+            _say(f"[gpu] rounds {pl.info['rounds']} stages {stages}: ms {[round(v / calls, 4) for v in ms]}")
+            assert calls == 3
+            assert all((v > 0) == (s in stages) for s, v in enumerate(ms))
+            assert all(torch.equal(o, ref) for o in outs)
+        img = ref.clone()
+        pl.timing_begin(2, stages=(1, 5))
+        for _ in range(2):
+            pl.forward(img)
+        ms, calls = pl.timing_end()
+        _say(f"[gpu] forward stages (1, 5): ms {[round(v / calls, 4) for v in ms]}")
+        assert calls == 2 and ms[1] > 0 and ms[5] > 0 and all(ms[s] == 0 for s in (0, 2, 3, 4))
+        for mask in (0, 1 << N.PAT_TIMING_STAGES):
+            with pytest.raises(PatError):
+                N.check(pl._lib.pat_timing_begin_stages(pl._handle, 2, mask), "pat_timing_begin_stages")
+        pl.close()
