@@ -126,7 +126,7 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     const int rows = patk::fft_batch<T>(d.n_x, cfg.threads, cfg.cap);
     if (rows * d.n_x > kFft || rows * d.Nx > kFft) return PAT_ERR_UNSUPPORTED;
     const int gx2 = (d.n_y + rows - 1) / rows;
-    a2[p] = patk::FftXBA{A, patk::as_view(d.f_nx), d.n_y, d.Nx, rows, gx2, Bw};
+    a2[p] = patk::FftXBA{A, patk::as_view(d.f_nx), d.n_y, d.Nx, rows, gx2, Bw, d.jrange ? d.brange : nullptr};
     pre[2][p + 1] = gx2 * d.nb;
     lds[2] = std::max(lds[2], (size_t(rows) * patk::lseq(d.n_x) + d.n_x) * c);
     // stage 3: FFT along y with deconvolution

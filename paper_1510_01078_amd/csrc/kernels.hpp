@@ -175,7 +175,7 @@ struct SpreadBA {
   int nb, n_x, n_y, tiles_x, nchunks; void* U;
 };
 struct FftXBA {
-  const void* U; FftView fd; int n_y, Nx, rows, gx; void* V;
+  const void* U; FftView fd; int n_y, Nx, rows, gx; void* V; const int* brange;
 };
 struct FftYBA {
   const void* V; const void* dcx; const void* dcy; FftView fd; int nb, Nx, Ny, bins, gx; void* Gh;

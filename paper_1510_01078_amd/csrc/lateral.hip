@@ -31,6 +31,13 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
     const int j = jj < Nx / 2 ? jj : jj - Nx;
     return lpos(j < 0 ? j + n_x : j);
   };
+  // only the x modes whose band range holds bin b (|j| in [J0, J1]) are
+  // written: the y-FFT and the interpolation read no others
+  const int J0 = brange ? brange[2 * b] : 0, J1 = brange ? brange[2 * b + 1] : Nx;
+  auto kept = [&](int jj) {
+    const int aj = jj < Nx / 2 ? jj : Nx - jj;
+    return aj >= J0 && aj <= J1;
+  };
   cx<T>* twl = buf + rows * bstride;
   if constexpr (NCT > 0) {
     // compile-time geometry (rows = ROWS, 256 threads): no index divisions
@@ -42,14 +49,7 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
     __syncthreads();
     fft_ct<T, NCT, kFftThreads, ROWS, false>(buf, nr, twl, tid);
     __syncthreads();
-    // V[b][jj][py0 + r]: neighbouring threads write neighbouring rows; only
-    // the x modes whose band range holds bin b (|j| in [J0, J1]): the y-FFT
-    // and the interpolation read no others
-    const int J0 = brange ? brange[2 * b] : 0, J1 = brange ? brange[2 * b + 1] : Nx;
-    auto kept = [&](int jj) {
-      const int aj = jj < Nx / 2 ? jj : Nx - jj;
-      return aj >= J0 && aj <= J1;
-    };
+    // V[b][jj][py0 + r]: neighbouring threads write neighbouring rows
     cx<T>* d0 = dst + size_t(tid / ROWS) * n_y + tid % ROWS;
     const size_t step = size_t(kFftThreads / ROWS) * n_y;
     staged_cols<ROWS, kFftThreads, (NCT * ROWS + kFftThreads - 1) / kFftThreads>(  // Nx < n_x = NCT
@@ -75,11 +75,11 @@ __device__ __forceinline__ void fft_x_body(const cx<T>* __restrict__ U, int n_y,
         nr * Nx, tid, nthr,
         [&](int q) {
           const int jj = div_nr(q);
-          return buf[(q - jj * nr) * bstride + slot(jj)];
+          return kept(jj) ? buf[(q - jj * nr) * bstride + slot(jj)] : cx<T>{T(0), T(0)};
         },
         [&](int q, cx<T> v) {
           const int jj = div_nr(q);
-          dst[size_t(jj) * n_y + (q - jj * nr)] = v;
+          if (kept(jj)) dst[size_t(jj) * n_y + (q - jj * nr)] = v;
         });
   }
 }
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_x_batch(const FftXBA* __res
     const int local = w - meta.prefix[p];
     const int by = local / a.gx;
     fft_x_body<T>(static_cast<const cx<T>*>(a.U), a.n_y, a.Nx, a.rows, 0, view_desc<T>(a.fd),
-                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by, nullptr, loop_lane());
+                  static_cast<cx<T>*>(a.V), 0, local - by * a.gx, by, a.brange, loop_lane());
     __syncthreads();
   }
 }
