@@ -140,7 +140,7 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     lds[3] = std::max(lds[3], (size_t(bins) * patk::lseq(d.n_y) + d.n_y) * c);
     // stage 4: temporal interpolation and weight (image-ready spectrum) fused
     // with the inverse transform along x
-    const int lcx = patk::fft_batch<T>(d.Nx, icfg.threads, icfg.cap);
+    const int lcx = patk::fft_batch<T>(d.Nx, icfg.threads, patk::kGatherCap);
     const int gx5 = (Lh + lcx - 1) / lcx;
     int wt_ct = 0;
     for (int t : patk::kBatchTaps)

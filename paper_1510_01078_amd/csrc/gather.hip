@@ -228,7 +228,7 @@ __device__ __forceinline__ void gather_x_body(const cx<T>* __restrict__ Gh, int 
   const FastDiv div_nl(nl);
   // (one loop form for every length: the batched reconstruction runs this
   // loop too, and the same code keeps the two paths' values bit for bit equal)
-  constexpr int ROWS = NCT > 0 ? ct_maxb(NCT, kInvCap) : 1;
+  constexpr int ROWS = NCT > 0 ? ct_maxb(NCT, kGatherCap) : 1;
   for (int q = tid; q < nl * Nx; q += nthr) {
     const int jj = div_nl(q);
     const int li = q - jj * nl;
@@ -301,7 +301,7 @@ hipError_t launch_gather_x(const DevPlan& p, const void* Gh, void* F, int mode, 
   if (p.w_t * (p.hdeg + 1) > kMaxTapCoefs) return hipErrorInvalidValue;
   const int Lh = p.Nz / 2 + 1;
   const FftCfg cfg = inv_cfg();
-  const int lc = fft_batch<T>(p.Nx, cfg.threads, cfg.cap);
+  const int lc = fft_batch<T>(p.Nx, cfg.threads, kGatherCap);
   const size_t lds = (size_t(lc) * lseq(p.Nx) + p.Nx) * sizeof(cx<T>);
   const dim3 grid((Lh + lc - 1) / lc, p.Ny);
   const cx<T>* in = static_cast<const cx<T>*>(Gh);
@@ -314,7 +314,7 @@ hipError_t launch_gather_x(const DevPlan& p, const void* Gh, void* F, int mode, 
     return ct_pick(CtInverse{}, p.Nx, [&](auto c) {
       constexpr int NCT = decltype(c)::value;
       // the compile-time kernels take their geometry from the length
-      if (NCT > 0 && (lc != ct_maxb(NCT, kInvCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
+      if (NCT > 0 && (lc != ct_maxb(NCT, kGatherCap) || cfg.threads != kFftThreads)) return hipErrorInvalidValue;
       const void* kern = adj ? reinterpret_cast<const void*>(&k_gather_x<T, MODE_ADJOINT, WT, NCT>)
                              : reinterpret_cast<const void*>(&k_gather_x<T, MODE_IMAGE, WT, NCT>);
       hipError_t e = allow_lds(kern, lds);
