@@ -46,8 +46,8 @@ static inline FftCfg fft_cfg() { return FftCfg{}; }
 constexpr int kInvCap = 16;
 // z modes per work-group of the gather fused with the inverse x pass: 8
 // (19.5 KiB of LDS at 256 points) fits 6 work-groups per CU where 16 fit 4,
-// and the gather is bound by instruction issue (0.083 -> 0.077 ms at the
-// headline size; 4 measured 0.088 ms)
+// and the gather is bound by instruction issue (0.083 -> 0.077 ms for a
+// 256^3 image from 576 band bins; 4 measured 0.088 ms)
 constexpr int kGatherCap = 8;
 static inline FftCfg inv_cfg() { return FftCfg{256, kInvCap, 0}; }
 
