@@ -161,7 +161,8 @@ pat_status build_group(pat_batch* B, BatchGroup& G, unsigned char* ws, hipStream
     const long long nrows = (long long)d.Nx * d.Ny;
     a6[p] = patk::C2rBA{Bw, patk::as_view(d.f_Nz), nrows, rz};
     pre[6][p + 1] = int((nrows + rz - 1) / rz);
-    lds[6] = std::max(lds[6], (size_t(rz) * patk::lseq(d.Nz) + d.Nz) * c);
+    if ((rz + 1) / 2 * (d.Nz / 2 + 1) > patk::kC2rStage * icfg.threads) return PAT_ERR_UNSUPPORTED;
+    lds[6] = std::max(lds[6], size_t(patk::c2r_lds_slots(rz, d.Nz)) * c);
   }
   for (auto& v : pre) {
     for (int p = 0; p < P; ++p) {

@@ -166,7 +166,12 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
   struct Two {
     cx<T> a, c;
   };
-  staged_copy<kFftMaxV>(
+  // values staged per thread: what the pairs of a compile-time length need
+  // (5 at 256 points), else kC2rStage; kFftMaxV held 64 registers for the
+  // pairs (launches check np * Lh <= kC2rStage * threads)
+  constexpr int UL = NCT > 0 ? ((ct_maxb(NCT, kInvCap) + 1) / 2 * (NCT / 2 + 1) + kFftThreads - 1) / kFftThreads
+                             : kC2rStage;
+  staged_copy<UL>(
       np * Lh, tid, nthr,
       [&](int q) {
         const int s = div_lh(q);
@@ -184,11 +189,15 @@ __device__ __forceinline__ void c2r_z_body(const cx<T>* __restrict__ F, long lon
           row[lpos(Nz - l)] = cx<T>{v.a.x + v.c.y, v.c.x - v.a.y};
         }
       });
-  cx<T>* twl = buf + rows * bstride;
+  // the sequences hold (rows + 1) / 2 pairs: the twiddles go behind them,
+  // and the transform is compiled for that many (with LDS and registers for
+  // `rows` sequences, half unused, the kernel held 100 registers and 37 KiB
+  // of LDS per work-group at 256 points: 4 per CU)
+  cx<T>* twl = buf + (rows + 1) / 2 * bstride;
   for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), true>(buf, np, twl, tid);
+    fft_ct<T, NCT, kFftThreads, (ct_maxb(NCT, kInvCap) + 1) / 2, true>(buf, np, twl, tid);
   else
     fft_group<T, true>(buf, lds_twiddles(fd, twl), np, bstride, tid, nthr, wm);
   __syncthreads();
@@ -298,8 +307,9 @@ hipError_t launch_inverse(const DevPlan& p, void* Fh, T* f, hipStream_t s, bool 
   if (e != hipSuccess) return e;
   const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
-  const size_t lds = (size_t(rows) * lseq(p.Nz) + p.Nz) * sizeof(cx<T>);
+  const size_t lds = size_t(c2r_lds_slots(rows, p.Nz)) * sizeof(cx<T>);
   const long long nrows = (long long)p.Nx * p.Ny;
+  if ((rows + 1) / 2 * (p.Nz / 2 + 1) > kC2rStage * cfg.threads) return hipErrorInvalidValue;
   return ct_pick(CtInverse{}, p.Nz, [&](auto c) {
     hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_c2r_z<T, decltype(c)::value>), lds);
     if (e2 != hipSuccess) return e2;

@@ -209,6 +209,14 @@ __device__ __forceinline__ int batch_locate(const int* prefix, int nprob, int w)
   return lo;
 }
 
+// LDS slots of a complex-to-real z work-group of `rows` real rows: two rows
+// share one complex sequence, then the n twiddles.
+__host__ __device__ constexpr int c2r_lds_slots(int rows, int n) { return (rows + 1) / 2 * lseq(n) + n; }
+// complex pairs staged per thread in a runtime-length complex-to-real z pass:
+// (rows + 1) / 2 pairs of n / 2 + 1 values with rows * n <= kFftMaxV * 256
+// stay within 8 * 256 for every n <= 2048 (at most 1366; 1032 at n = 256)
+constexpr int kC2rStage = 8;
+
 // LDS slots of one temporal work-group (a sensor pair): the sequence, then
 // the split twiddle tables (single-problem and batched launches).
 __host__ __device__ constexpr int temporal_lds_slots(int n_t) { return lseq(n_t) + tw_split_slots(n_t); }
