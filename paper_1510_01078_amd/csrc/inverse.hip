@@ -218,7 +218,11 @@ __global__ __launch_bounds__(kFftThreads) void k_c2r_z(const cx<T>* __restrict__
 }
 
 // Transpose of k_c2r_z for the forward model: real rows f[r][e] ->
-// Dh[r][l] = sum_e f[r][e] exp(-2 pi i l e/Nz), l = 0..Nz/2.
+// Dh[r][l] = sum_e f[r][e] exp(-2 pi i l e/Nz), l = 0..Nz/2. Two real rows
+// share one complex transform, Z = FFT(x0 + i x1): X0[l] = (Z[l] + conj
+// Z[-l])/2 and X1[l] = (Z[l] - conj Z[-l])/(2i), so a work-group of `rows`
+// rows transforms (rows + 1) / 2 sequences (half the transforms, LDS and
+// registers of one sequence per row).
 template <typename T, int NCT>
 __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, long long nrows, int rows,
                                                      FftDesc<T> fd, cx<T>* __restrict__ D) {
@@ -230,29 +234,48 @@ __global__ __launch_bounds__(kFftThreads) void k_r2c_z(const T* __restrict__ f, 
   const int bstride = lseq(Nz);
   const long long r0 = (long long)blockIdx.x * rows;
   const int nr = (int)min((long long)rows, nrows - r0);
+  const int np = (nr + 1) / 2;
   const FastDiv fdiv_lh(Lh), fdiv_nz(Nz);
   // compile-time lengths divide by constants (a shift for Nz)
   auto div_lh = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT / 2 + 1)) : fdiv_lh(q); };
   auto div_nz = [&](int q) { return NCT > 0 ? int(unsigned(q) / unsigned(NCT > 0 ? NCT : 1)) : fdiv_nz(q); };
-  staged_copy<kFftMaxV>(
-      nr * Nz, tid, nthr, [&](int q) { return f[r0 * Nz + q]; },
-      [&](int q, T v) {
-        const int r = div_nz(q);
-        buf[r * bstride + lpos(q - r * Nz)] = cx<T>{v, T(0)};
+  struct Two {
+    T a, b;
+  };
+  // values staged per thread: what a compile-time length needs, else
+  // kFftMaxV (np * Nz <= rows * Nz / 2 + Nz / 2 <= 3 * 1024 by fft_batch)
+  constexpr int ROWS = NCT > 0 ? ct_maxb(NCT, kInvCap) : 1;
+  constexpr int UL = NCT > 0 ? ((ROWS + 1) / 2 * NCT + kFftThreads - 1) / kFftThreads : kFftMaxV;
+  constexpr int UO = NCT > 0 ? (ROWS * (NCT / 2 + 1) + kFftThreads - 1) / kFftThreads : kFftMaxV;
+  staged_copy<UL>(
+      np * Nz, tid, nthr,
+      [&](int q) {
+        const int s = div_nz(q);
+        const long long at = (r0 + 2 * s) * Nz + (q - s * Nz);
+        return Two{f[at], 2 * s + 1 < nr ? f[at + Nz] : T(0)};
+      },
+      [&](int q, Two v) {
+        const int s = div_nz(q);
+        buf[s * bstride + lpos(q - s * Nz)] = cx<T>{v.a, v.b};
       });
-  cx<T>* twl = buf + rows * bstride;
+  cx<T>* twl = buf + (rows + 1) / 2 * bstride;
   for (int t = tid; t < (NCT > 0 ? NCT : fd.n); t += nthr) twl[t] = fd.tw[t];
   __syncthreads();
   if constexpr (NCT > 0)
-    fft_ct<T, NCT, kFftThreads, ct_maxb(NCT, kInvCap), false>(buf, nr, twl, tid);
+    fft_ct<T, NCT, kFftThreads, (ROWS + 1) / 2, false>(buf, np, twl, tid);
   else
-    fft_lds<T, kFftMaxV, false, false>(buf, lds_twiddles(fd, twl), nr, bstride, tid, nthr);
+    fft_lds<T, kFftMaxV, false, false>(buf, lds_twiddles(fd, twl), np, bstride, tid, nthr);
   __syncthreads();
-  staged_copy<kFftMaxV>(
+  staged_copy<UO>(
       nr * Lh, tid, nthr,
       [&](int q) {
         const int r = div_lh(q);
-        return buf[r * bstride + lpos(q - r * Lh)];
+        const int l = q - r * Lh;
+        const cx<T>* row = buf + (r >> 1) * bstride;
+        const cx<T> z = row[lpos(l)];
+        const cx<T> zm = row[lpos(l == 0 ? 0 : Nz - l)];
+        return (r & 1) ? cx<T>{T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)}
+                       : cx<T>{T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
       },
       [&](int q, cx<T> v) { D[r0 * Lh + q] = v; });
 }
@@ -324,8 +347,10 @@ hipError_t launch_forward3d(const DevPlan& p, const T* f, void* Dh, hipStream_t 
   cx<T>* D = static_cast<cx<T>*>(Dh);
   const FftCfg cfg = inv_cfg();
   const int rows = fft_batch<T>(p.Nz, cfg.threads, cfg.cap);
-  const size_t lds = (size_t(rows) * lseq(p.Nz) + p.Nz) * sizeof(cx<T>);
+  const size_t lds = size_t(c2r_lds_slots(rows, p.Nz)) * sizeof(cx<T>);  // (rows + 1) / 2 sequences
   const long long nrows = (long long)p.Nx * p.Ny;
+  if ((rows + 1) / 2 * p.Nz > kFftMaxV * cfg.threads || rows * (p.Nz / 2 + 1) > kFftMaxV * cfg.threads)
+    return hipErrorInvalidValue;
   hipError_t e = ct_pick(CtInverse{}, p.Nz, [&](auto c) {
     hipError_t e2 = allow_lds(reinterpret_cast<const void*>(&k_r2c_z<T, decltype(c)::value>), lds);
     if (e2 != hipSuccess) return e2;
